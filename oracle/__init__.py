@@ -1,0 +1,22 @@
+"""CPU FP64 oracle for the row-wise decomposed multi-dimensional FFT of
+Duy & Ozaki, "A decomposition method with minimum communication amount for
+parallelization of multi-dimensional FFTs".
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import, call or link anything here;
+the product library never does, and shares no code with it.
+
+Modules
+-------
+dft        Eqs. (1)-(2): brute-force DFT, recursive mixed-radix FFT (C),
+           axis-by-axis M-D FFT, error metrics.
+decomp     Eqs. (4)-(19): levels, ranges, start/end points, owners point by
+           point, communication amounts (readings R1 and R2), Eqs. (21)-(25).
+orders     Eq. (20) / Table 1: valid transpose orders and their enumeration.
+pipeline   Fig. 4 with explicit per-process arrays and an all-to-all.
+
+Parity status: every function is pinned by a test against values the paper
+prints, closed forms, textbook identities or brute force, except the handling
+of the row-split regime (level M), which the paper leaves undefined and the
+oracle refuses (parity unpinned: not implemented).
+"""
