@@ -1,0 +1,247 @@
+/*
+ * fftrw.h -- row-wise decomposed multi-dimensional complex FFTs on one MI355X.
+ *
+ * Implements the parallel M-D FFT of Duy & Ozaki, "A decomposition method with
+ * minimum communication amount for parallelization of multi-dimensional FFTs":
+ * N_p processes each own a contiguous 1-D range of the array in the current
+ * axis order (the row-wise adaptive decomposition, Eqs. (12)-(19)); step t
+ * runs 1-D FFTs (Eq. (1)) along the last axis of decomposition pi_t and then
+ * transposes to pi_{t+1}, re-decomposing (Fig. 4).  Here all N_p processes
+ * are *virtual*: their ranges are consecutive slices of one device buffer, so
+ * every transpose is an on-device permutation through HBM whose count of
+ * points that change owner is the paper's communication amount.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * - M in [2, 5]; dims[0..M) = (N_1, ..., N_M), N_1 slowest (row-major, C order).
+ * - An axis permutation `perm` (M int8) lists natural axis indices from the
+ *   slowest to the fastest position: {2,0,1} is the paper's "cab".
+ * - A transpose order `order` (M*M int8) is M permutations, row t = pi_{t+1}:
+ *   order[t*M + i] = natural axis at position i of decomposition t.  Row 0 must
+ *   be the identity and the last entries of the M rows must all differ (the
+ *   FFT axis of each step; Section 3.2, Eq. (20)).
+ * - Complex data are interleaved (re, im).  FFTRW_C64 = 2 x float, FFTRW_C128 =
+ *   2 x double.  Forward uses w_N = exp(-2 pi i / N) with no scaling (Eq. (1));
+ *   inverse uses exp(+2 pi i / N) and scales by 1/T, T = prod(dims).
+ * - Every function returns an int status (0 = FFTRW_OK, < 0 = error) unless
+ *   stated otherwise; no C++ exception crosses this interface.  The text of the
+ *   last error on the calling thread is returned by fft_last_error().
+ * - Pointers named `in`/`out` and the `stream` argument are HIP device
+ *   pointers and a hipStream_t (NULL = the default stream).  Host pointers are
+ *   named otherwise and are only read/written during the call.
+ */
+#ifndef FFTRW_H
+#define FFTRW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+enum {
+    FFTRW_OK = 0,
+    FFTRW_E_ARG = -1,         /* null pointer, bad enum, bad index            */
+    FFTRW_E_SIZE = -2,        /* M not in [2,5], a size < 1, or a row length the
+                                 FFT kernels do not support (see fft_plan)     */
+    FFTRW_E_ORDER = -3,       /* malformed permutation or transpose order      */
+    FFTRW_E_ROWSPLIT = -4,    /* N_p > T / N_last for some step: rows along the
+                                 FFT axis would be split over processes (level M
+                                 of Eq. (13)); the paper leaves that case open  */
+    FFTRW_E_NOMEM = -5,       /* host or device allocation failed             */
+    FFTRW_E_DEVICE = -6,      /* a HIP call failed; see fft_last_error()       */
+    FFTRW_E_UNSUPPORTED = -7  /* combination not implemented                   */
+};
+
+/* ---- enums ----------------------------------------------------------------- */
+enum { FFTRW_C64 = 1, FFTRW_C128 = 2 };
+
+enum {
+    FFTRW_PREC_NATIVE = 0,        /* FP32 math for C64, FP64 math for C128        */
+    FFTRW_PREC_SPLIT_F16 = 1,     /* radix-16 stages on FP16 MFMA, hi/lo split    */
+    FFTRW_PREC_SPLIT_BF16 = 2,    /* radix-16 stages on BF16 MFMA, hi/lo split    */
+    FFTRW_PREC_SPLIT_BF16X3 = 3   /* radix-16 stages on BF16 MFMA, 3-term split   */
+};
+
+enum { FFTRW_OWN_LITERAL = 0, FFTRW_OWN_MATCHED = 1 };
+
+enum {
+    FFTRW_FLAG_LEAVE_PERMUTED = 1u,  /* skip the final transpose back to natural
+                                        order: output stays in layout pi_M       */
+    FFTRW_FLAG_STAGED = 2u,          /* transposes as pack -> exchange -> unpack
+                                        with explicit per-process send/receive
+                                        segments (default: one fused permutation) */
+    FFTRW_FLAG_COUNT_MOVED = 4u,     /* count, on the device, the points whose
+                                        owner changes in every transpose          */
+    FFTRW_FLAG_OWN_MATCHED = 8u,     /* ownership reading R2 (see fft_comm_volume)*/
+    FFTRW_FLAG_FUSED_FFT = 16u       /* fuse each FFT step with the transpose that
+                                        follows it (one HBM pass per step)        */
+};
+
+typedef struct fft_plan_s *fft_plan_t;
+
+/* ---- host-only integer functions (no device needed) ----------------------- */
+
+/*
+ * fft_decomp -- Eqs. (13)-(19): the range of process `myid` in decomposition
+ * `perm` of an array of sizes `dims` over P processes.
+ *   level : k of Eq. (13) (1-based): the smallest k with P <= N'_1 ... N'_k,
+ *           where N'_i = dims[perm[i]].
+ *   xs,xe : first and last 1-D index (Eq. (12) in the order perm), inclusive.
+ *   start,end (M int64 each, nullable): Eqs. (16)-(19), coordinates in the
+ *           permuted order (start[i] runs along natural axis perm[i]).
+ * Errors: FFTRW_E_ARG (myid out of [0,P), null level/xs/xe), FFTRW_E_SIZE,
+ * FFTRW_E_ORDER (perm not a permutation), FFTRW_E_ROWSPLIT if P > T.
+ */
+int fft_decomp(int M, const int64_t *dims, int64_t P, const int8_t *perm,
+               int64_t myid, int *level, int64_t *xs, int64_t *xe,
+               int64_t *start, int64_t *end);
+
+/*
+ * fft_comm_volume -- the communication amount of a transpose order
+ * (Sections 3.1 and 3.3; the quantity compared in Section 4).
+ *   per_step[M-1] (nullable): points that change owner in transpose
+ *       pi_t -> pi_{t+1}, t = 1..M-1.
+ *   total: sum of per_step.
+ *   return_volume (nullable): the same count for the final transpose
+ *       pi_M -> natural order of Fig. 4, which is NOT part of `total`.
+ * ownership FFTRW_OWN_LITERAL (R1): process p owns range p of Eqs. (14)-(15)
+ *   in every decomposition.  FFTRW_OWN_MATCHED (R2): the ranges of each new
+ *   decomposition are assigned to processes one-to-one so that the most
+ *   points stay put (maximum-weight matching on the overlap counts).
+ * Counts are exact int64.  Row-split orders (level M) are still counted, and
+ * the call returns FFTRW_E_ROWSPLIT after filling the outputs.
+ */
+int fft_comm_volume(int M, const int64_t *dims, int64_t P, const int8_t *order,
+                    int ownership, int64_t *per_step, int64_t *total,
+                    int64_t *return_volume);
+
+/*
+ * fft_pair_counts -- overlap counts C[p][q] = points owned by p in
+ * decomposition perm_a and by q in perm_b (literal ownership), written densely
+ * into C[P*P] (host, caller-owned).  For checking; P <= 4096.
+ */
+int fft_pair_counts(int M, const int64_t *dims, int64_t P, const int8_t *perm_a,
+                    const int8_t *perm_b, int64_t *C);
+
+/* (M-1)!^M, the number of transpose orders (Eq. (20), Table 1); -1 if M is
+ * outside [2, 6]. */
+int64_t fft_order_count(int M);
+
+/* Order number `index` (0-based) in canonical enumeration: (pi_2, ..., pi_M)
+ * in lexicographic order, each permutation compared as a string over
+ * "abcde".  order: M*M int8 output (host). */
+int fft_order_at(int M, int64_t index, int8_t *order);
+
+/* Inverse of fft_order_at; FFTRW_E_ORDER if the order is not valid. */
+int fft_order_index(int M, const int8_t *order, int64_t *index);
+
+/*
+ * fft_order_search -- exhaustive search over all (M-1)!^M orders for the
+ * smallest and largest total communication amount (Sections 3.1, 3.3).
+ * Ties go to the lowest canonical index; n_best / n_worst count the tied
+ * orders.  best_order / worst_order (M*M int8, nullable) receive the orders.
+ * The best order is the one fft_plan uses when given order == NULL.
+ */
+int fft_order_search(int M, const int64_t *dims, int64_t P, int ownership,
+                     int64_t *best_index, int64_t *best_volume, int64_t *n_best,
+                     int64_t *worst_index, int64_t *worst_volume, int64_t *n_worst,
+                     int8_t *best_order, int8_t *worst_order);
+
+/*
+ * fft_order_volumes -- total amount of every order (host array of
+ * fft_order_count(M) int64, in canonical order).
+ */
+int fft_order_volumes(int M, const int64_t *dims, int64_t P, int ownership,
+                      int64_t *volumes);
+
+/*
+ * fft_compare_models -- the amounts of the fixed-degree methods compared in
+ * Section 4 for an N^M array: Eq. (21) 1-D (slab), Eq. (22) 2-D (pencil),
+ * Eq. (23) 3-D, Eq. (24) 4-D, Eq. (25) 5-D, evaluated as printed in double
+ * precision.  out[5] receives A_1D, A_2D, A_3D, A_4D, A_5D (the 1-D, 2-D and
+ * 3-D forms are stated for M = 3, the 4-D form for M = 4 and the 5-D form for
+ * M = 5; each is returned as printed regardless of M).
+ */
+int fft_compare_models(double N, double P, double *out);
+
+/* ---- plans and device execution ------------------------------------------ */
+
+/*
+ * fft_plan -- build an execution plan on the current HIP device.
+ *   order: M*M int8 as above, or NULL for the best order of fft_order_search
+ *          (literal ownership, lowest canonical index on ties).
+ *   dtype: FFTRW_C64 or FFTRW_C128.   precision: FFTRW_PREC_*; the split MFMA
+ *          forms need dtype C64 and every FFT axis a power of two >= 16.
+ *   flags: FFTRW_FLAG_*.
+ * Row lengths: every dims[i] must factor into 2, 3, 5 and be <= 4096.
+ * The plan owns its device workspace (fft_workspace_bytes) and twiddle
+ * tables; it must outlive every exec enqueued with it.  One exec per plan may
+ * be in flight at a time.
+ * Errors: FFTRW_E_ARG, FFTRW_E_SIZE, FFTRW_E_ORDER, FFTRW_E_ROWSPLIT,
+ * FFTRW_E_UNSUPPORTED, FFTRW_E_NOMEM, FFTRW_E_DEVICE.
+ */
+int fft_plan(fft_plan_t *plan, int M, const int64_t *dims, int64_t P,
+             const int8_t *order, int dtype, int precision, unsigned flags);
+
+/*
+ * fft_exec_fwd / fft_exec_inv -- enqueue the whole Fig. 4 pipeline on
+ * `stream`: for t = 1..M, 1-D FFTs along the last axis of pi_t, then the
+ * transpose to pi_{t+1} (to natural order after step M unless
+ * LEAVE_PERMUTED).  in: T elements in natural layout; out: T elements in
+ * natural layout (or pi_M layout with LEAVE_PERMUTED).  in == out is allowed;
+ * otherwise `in` is not modified.  Asynchronous: returns after enqueueing.
+ */
+int fft_exec_fwd(fft_plan_t plan, const void *in, void *out, void *stream);
+int fft_exec_inv(fft_plan_t plan, const void *in, void *out, void *stream);
+
+/*
+ * fft_exec_fft_step -- enqueue only step t (0-based) of the pipeline: 1-D FFTs
+ * along the last axis of pi_{t+1}.  in/out hold T elements in that layout
+ * (in == out allowed).  direction: -1 forward, +1 inverse (unscaled).
+ */
+int fft_exec_fft_step(fft_plan_t plan, int t, int direction, const void *in,
+                      void *out, void *stream);
+
+/*
+ * fft_exec_transpose -- enqueue only transpose t (0-based): layout pi_{t+1}
+ * -> pi_{t+2}, or pi_M -> natural for t = M-1, with the plan's mode (fused or
+ * staged) and counter.  in and out must not overlap.
+ */
+int fft_exec_transpose(fft_plan_t plan, int t, const void *in, void *out,
+                       void *stream);
+
+/*
+ * fft_plan_stats -- host copies of the plan's analytic amounts and the
+ * device counters of the last exec.
+ *   per_step[M] (nullable): analytic counts for transposes 1..M-1, then the
+ *       return transpose (the same numbers as fft_comm_volume).
+ *   moved[M] (nullable): points counted on the device as changing owner in
+ *       each transpose of the last exec (COUNT_MOVED), or the points copied by
+ *       the exchange kernel (STAGED); -1 where nothing was counted.  This call
+ *       synchronises the device.
+ */
+int fft_plan_stats(fft_plan_t plan, int64_t *per_step, int64_t *moved);
+
+/* Device bytes the plan holds (workspace, staging, tables). */
+int fft_workspace_bytes(fft_plan_t plan, size_t *bytes);
+
+/* Information about the plan: its order (M*M int8), and per step the radix
+ * factorisation of the FFT axis as a string "8x8x8" (buffer of `cap` bytes). */
+int fft_plan_describe(fft_plan_t plan, int8_t *order, char *text, size_t cap);
+
+int fft_destroy(fft_plan_t plan);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *fft_last_error(void);
+
+/* Library version string. */
+const char *fft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFTRW_H */

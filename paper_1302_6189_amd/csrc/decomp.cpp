@@ -1,0 +1,520 @@
+// decomp.cpp -- host integer model of the row-wise adaptive decomposition.
+//
+// Section 3 of Duy & Ozaki: each process owns the contiguous 1-D range
+// [f(myid), f(myid+1) - 1] of Eqs. (13)-(15) in the current axis order; a
+// transpose re-decomposes in the next order.  The amount of a transpose is
+// the number of points whose owner changes.  Here it is counted analytically:
+// a process's range is a union of at most 2k-1 axis-aligned boxes, so the
+// kept points are box intersections instead of a walk over every point.
+#include "decomp.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <limits>
+#include <numeric>
+
+namespace fftrw {
+
+i64 box_volume(const Box &b, int M)
+{
+    i64 v = 1;
+    for (int d = 0; d < M; ++d) {
+        if (b.hi[d] < b.lo[d]) return 0;
+        v *= b.hi[d] - b.lo[d] + 1;
+    }
+    return v;
+}
+
+bool box_intersect(const Box &a, const Box &b, int M, Box *out)
+{
+    for (int d = 0; d < M; ++d) {
+        i64 lo = std::max(a.lo[d], b.lo[d]);
+        i64 hi = std::min(a.hi[d], b.hi[d]);
+        if (hi < lo) return false;
+        if (out) {
+            out->lo[d] = lo;
+            out->hi[d] = hi;
+        }
+    }
+    return true;
+}
+
+i64 box_overlap(const Box &a, const Box &b, int M)
+{
+    i64 v = 1;
+    for (int d = 0; d < M; ++d) {
+        i64 lo = std::max(a.lo[d], b.lo[d]);
+        i64 hi = std::min(a.hi[d], b.hi[d]);
+        if (hi < lo) return 0;
+        v *= hi - lo + 1;
+    }
+    return v;
+}
+
+Status check_dims(int M, const i64 *dims)
+{
+    if (M < 2 || M > kMaxDims) return Status::err(-2, "M must be in [2, 5]");
+    if (!dims) return Status::err(-1, "dims is null");
+    __int128 T = 1;
+    for (int d = 0; d < M; ++d) {
+        if (dims[d] < 1) return Status::err(-2, "every size must be >= 1");
+        T *= dims[d];
+        if (T > ((__int128)1 << 62)) return Status::err(-2, "too many points");
+    }
+    return Status::ok();
+}
+
+Status check_perm(int M, const int8_t *perm)
+{
+    if (!perm) return Status::err(-1, "permutation is null");
+    bool seen[kMaxDims] = {};
+    for (int i = 0; i < M; ++i) {
+        int a = perm[i];
+        if (a < 0 || a >= M || seen[a]) return Status::err(-3, "not a permutation of the axes");
+        seen[a] = true;
+    }
+    return Status::ok();
+}
+
+Status check_order(int M, const int8_t *order)
+{
+    if (!order) return Status::err(-1, "order is null");
+    for (int i = 0; i < M; ++i)
+        if (order[i] != i) return Status::err(-3, "the first decomposition must be the natural order");
+    bool last_used[kMaxDims] = {};
+    for (int t = 0; t < M; ++t) {
+        Status s = check_perm(M, order + t * M);
+        if (!s) return s;
+        int last = order[t * M + M - 1];
+        if (last_used[last]) return Status::err(-3, "two steps transform the same axis");
+        last_used[last] = true;
+    }
+    return Status::ok();
+}
+
+Status make_layout(int M, const i64 *dims, i64 P, const int8_t *perm, Layout *out)
+{
+    Status s = check_dims(M, dims);
+    if (!s) return s;
+    s = check_perm(M, perm);
+    if (!s) return s;
+    if (P < 1) return Status::err(-1, "P must be >= 1");
+    Layout L;
+    L.M = M;
+    L.P = P;
+    L.T = 1;
+    for (int i = 0; i < M; ++i) {
+        L.perm[i] = perm[i];
+        L.pos[perm[i]] = i;
+        L.pd[i] = dims[perm[i]];
+        L.T *= L.pd[i];
+    }
+    if (P > L.T) return Status::err(-4, "P exceeds the number of points");
+    i64 acc = 1;
+    L.k = 0;
+    for (int i = 0; i < M; ++i) {
+        acc *= L.pd[i];
+        if (P <= acc) {
+            L.k = i + 1;
+            L.R = acc;
+            break;
+        }
+    }
+    L.W = L.T / L.R;
+    i64 st = 1;
+    for (int i = M - 1; i >= 0; --i) {
+        L.stride[L.perm[i]] = st;
+        st *= L.pd[i];
+    }
+    *out = L;
+    return Status::ok();
+}
+
+void range_of(const Layout &L, i64 p, i64 *xs, i64 *xe, i64 *start, i64 *end)
+{
+    i64 s = L.boundary(p);
+    i64 e = L.boundary(p + 1) - 1;
+    if (xs) *xs = s;
+    if (xe) *xe = e;
+    // Eqs. (16)-(19): successive floor divisions in the permuted order
+    auto split = [&](i64 x, i64 *c) {
+        if (!c) return;
+        i64 w = L.T;
+        for (int r = 0; r < L.M; ++r) {
+            w /= L.pd[r];
+            c[r] = x / w;
+            x -= c[r] * w;
+        }
+    };
+    split(s, start);
+    split(e, end);
+}
+
+namespace {
+
+// Emit boxes covering rows [a, b] (lexicographic over positions d..k-1 of the
+// permuted order; positions < d already fixed in `cur`).
+void row_boxes(const Layout &L, int d, i64 a, i64 b, Box cur, std::vector<Box> &out)
+{
+    if (a > b) return;
+    const int k = L.k;
+    const int ax = L.perm[d];
+    if (d == k - 1) {
+        cur.lo[ax] = a;
+        cur.hi[ax] = b;
+        out.push_back(cur);
+        return;
+    }
+    i64 stride = 1;
+    for (int i = d + 1; i < k; ++i) stride *= L.pd[i];
+    i64 a0 = a / stride, ar = a % stride;
+    i64 b0 = b / stride, br = b % stride;
+    if (a0 == b0) {
+        cur.lo[ax] = cur.hi[ax] = a0;
+        row_boxes(L, d + 1, ar, br, cur, out);
+        return;
+    }
+    if (ar != 0) {
+        Box h = cur;
+        h.lo[ax] = h.hi[ax] = a0;
+        row_boxes(L, d + 1, ar, stride - 1, h, out);
+        ++a0;
+    }
+    bool tail = br != stride - 1;
+    i64 mid_hi = tail ? b0 - 1 : b0;
+    if (a0 <= mid_hi) {
+        Box m = cur;
+        m.lo[ax] = a0;
+        m.hi[ax] = mid_hi;
+        for (int i = d + 1; i < k; ++i) {
+            m.lo[L.perm[i]] = 0;
+            m.hi[L.perm[i]] = L.pd[i] - 1;
+        }
+        out.push_back(m);
+    }
+    if (tail) {
+        Box t = cur;
+        t.lo[ax] = t.hi[ax] = b0;
+        row_boxes(L, d + 1, 0, br, t, out);
+    }
+}
+
+}  // namespace
+
+std::vector<Box> range_boxes(const Layout &L, i64 p)
+{
+    std::vector<Box> out;
+    Box cur;
+    for (int i = 0; i < L.M; ++i) {
+        cur.lo[L.perm[i]] = 0;
+        cur.hi[L.perm[i]] = L.pd[i] - 1;
+    }
+    i64 r0 = L.row_lo(p), r1 = L.row_lo(p + 1) - 1;
+    row_boxes(L, 0, r0, r1, cur, out);
+    return out;
+}
+
+i64 kept_literal(const Layout &a, const Layout &b)
+{
+    i64 kept = 0;
+    for (i64 p = 0; p < a.P; ++p) {
+        std::vector<Box> ba = range_boxes(a, p);
+        std::vector<Box> bb = range_boxes(b, p);
+        for (const Box &x : ba)
+            for (const Box &y : bb) kept += box_overlap(x, y, a.M);
+    }
+    return kept;
+}
+
+bool product_set_successor(int k, const i64 *l, const i64 *h, const i64 *n, i64 v, i64 *out)
+{
+    i64 w[kMaxDims];
+    w[k - 1] = 1;
+    for (int i = k - 2; i >= 0; --i) w[i] = w[i + 1] * n[i + 1];
+    if (v >= w[0] * n[0]) return false;
+    i64 d[kMaxDims];
+    i64 rem = v;
+    for (int i = 0; i < k; ++i) {
+        d[i] = rem / w[i];
+        rem -= d[i] * w[i];
+    }
+    for (int i = 0; i < k; ++i) {
+        if (d[i] < l[i]) {
+            for (int j = i; j < k; ++j) d[j] = l[j];
+            break;
+        }
+        if (d[i] > h[i]) {
+            int j = i - 1;
+            while (j >= 0 && d[j] >= h[j]) --j;
+            if (j < 0) return false;
+            d[j] += 1;
+            for (int m = j + 1; m < k; ++m) d[m] = l[m];
+            break;
+        }
+    }
+    i64 s = 0;
+    for (int i = 0; i < k; ++i) s += d[i] * w[i];
+    *out = s;
+    return true;
+}
+
+std::vector<PairCount> pair_counts(const Layout &a, const Layout &b)
+{
+    std::vector<PairCount> out;
+    std::vector<std::pair<i64, i64>> acc;
+    for (i64 p = 0; p < a.P; ++p) {
+        acc.clear();
+        for (const Box &B : range_boxes(a, p)) {
+            for_each_owner(b, B, [&](i64 q) {
+                i64 n = 0;
+                for (const Box &C : range_boxes(b, q)) n += box_overlap(B, C, a.M);
+                if (n) acc.emplace_back(q, n);
+            });
+        }
+        std::sort(acc.begin(), acc.end());
+        for (size_t i = 0; i < acc.size();) {
+            i64 q = acc[i].first, n = 0;
+            while (i < acc.size() && acc[i].first == q) n += acc[i++].second;
+            out.push_back({p, q, n});
+        }
+    }
+    return out;
+}
+
+namespace {
+
+// Dense Hungarian algorithm (minimum cost, potentials), n x n, 1-based
+// internally.  Returns col_of_row (0-based).
+std::vector<int> hungarian_min(int n, const std::vector<i64> &cost)
+{
+    const i64 INF = std::numeric_limits<i64>::max() / 4;
+    std::vector<i64> u(n + 1, 0), v(n + 1, 0), minv(n + 1);
+    std::vector<int> pr(n + 1, 0), way(n + 1, 0);
+    std::vector<char> used(n + 1);
+    for (int i = 1; i <= n; ++i) {
+        pr[0] = i;
+        int j0 = 0;
+        std::fill(minv.begin(), minv.end(), INF);
+        std::fill(used.begin(), used.end(), 0);
+        do {
+            used[j0] = 1;
+            int i0 = pr[j0], j1 = 0;
+            i64 delta = INF;
+            for (int j = 1; j <= n; ++j) {
+                if (used[j]) continue;
+                i64 cur = cost[(size_t)(i0 - 1) * n + (j - 1)] - u[i0] - v[j];
+                if (cur < minv[j]) {
+                    minv[j] = cur;
+                    way[j] = j0;
+                }
+                if (minv[j] < delta) {
+                    delta = minv[j];
+                    j1 = j;
+                }
+            }
+            for (int j = 0; j <= n; ++j) {
+                if (used[j]) {
+                    u[pr[j]] += delta;
+                    v[j] -= delta;
+                } else {
+                    minv[j] -= delta;
+                }
+            }
+            j0 = j1;
+        } while (pr[j0] != 0);
+        do {
+            int j1 = way[j0];
+            pr[j0] = pr[j1];
+            j0 = j1;
+        } while (j0);
+    }
+    std::vector<int> col_of_row(n, -1);
+    for (int j = 1; j <= n; ++j)
+        if (pr[j] > 0) col_of_row[pr[j] - 1] = j - 1;
+    return col_of_row;
+}
+
+struct DSU {
+    std::vector<i64> par;
+    explicit DSU(i64 n) : par(n) { std::iota(par.begin(), par.end(), 0); }
+    i64 find(i64 x)
+    {
+        while (par[x] != x) x = par[x] = par[par[x]];
+        return x;
+    }
+    void unite(i64 a, i64 b) { par[find(a)] = find(b); }
+};
+
+}  // namespace
+
+Status max_matching(i64 P, const std::vector<PairCount> &pc, i64 *weight, std::vector<i64> *mu)
+{
+    // Components of the bipartite overlap graph (rows 0..P-1, columns P..2P-1)
+    // are matched independently; nodes left over are paired by zero-weight
+    // entries, which does not change the optimum.
+    DSU dsu(2 * P);
+    for (const PairCount &e : pc) dsu.unite(e.p, P + e.q);
+    std::vector<std::vector<i64>> rows_of(2 * P), cols_of(2 * P);
+    for (i64 p = 0; p < P; ++p) rows_of[dsu.find(p)].push_back(p);
+    for (i64 q = 0; q < P; ++q) cols_of[dsu.find(P + q)].push_back(q);
+    std::vector<std::vector<PairCount>> edges_of(2 * P);
+    for (const PairCount &e : pc) edges_of[dsu.find(e.p)].push_back(e);
+
+    std::vector<i64> m(P, -1);
+    std::vector<char> col_taken(P, 0);
+    i64 total = 0;
+    for (i64 c = 0; c < 2 * P; ++c) {
+        if (edges_of[c].empty()) continue;
+        const auto &R = rows_of[c];
+        const auto &C = cols_of[c];
+        i64 n = std::max<i64>((i64)R.size(), (i64)C.size());
+        if (n > kMaxMatchP)
+            return Status::err(-7, "matched ownership: overlap component too large for the exact solver");
+        std::vector<i64> ridx(P, -1), cidx(P, -1);
+        for (size_t i = 0; i < R.size(); ++i) ridx[R[i]] = (i64)i;
+        for (size_t j = 0; j < C.size(); ++j) cidx[C[j]] = (i64)j;
+        std::vector<i64> cost((size_t)(n * n), 0);
+        for (const PairCount &e : edges_of[c]) cost[(size_t)(ridx[e.p] * n + cidx[e.q])] = -e.n;
+        std::vector<int> col = hungarian_min((int)n, cost);
+        for (size_t i = 0; i < R.size(); ++i) {
+            int j = col[i];
+            if (j >= 0 && j < (int)C.size()) {
+                i64 w = -cost[(size_t)(i * n + j)];
+                if (w > 0) {
+                    m[R[i]] = C[j];
+                    col_taken[C[j]] = 1;
+                    total += w;
+                }
+            }
+        }
+    }
+    // complete the permutation with the remaining (zero-overlap) pairs
+    i64 next_free = 0;
+    for (i64 p = 0; p < P; ++p) {
+        if (m[p] >= 0) continue;
+        // prefer keeping the same label when it is free
+        if (!col_taken[p]) {
+            m[p] = p;
+            col_taken[p] = 1;
+        }
+    }
+    for (i64 p = 0; p < P; ++p) {
+        if (m[p] >= 0) continue;
+        while (col_taken[next_free]) ++next_free;
+        m[p] = next_free;
+        col_taken[next_free] = 1;
+    }
+    if (weight) *weight = total;
+    if (mu) *mu = std::move(m);
+    return Status::ok();
+}
+
+Status transpose_amount(const Layout &a, const Layout &b, int ownership, i64 *moved,
+                        std::vector<i64> *mu)
+{
+    if (ownership == 0) {
+        *moved = a.T - kept_literal(a, b);
+        if (mu) {
+            mu->resize(a.P);
+            std::iota(mu->begin(), mu->end(), 0);
+        }
+        return Status::ok();
+    }
+    if (ownership != 1) return Status::err(-1, "unknown ownership reading");
+    i64 w = 0;
+    Status s = max_matching(a.P, pair_counts(a, b), &w, mu);
+    if (!s) return s;
+    *moved = a.T - w;
+    return Status::ok();
+}
+
+// ---- orders -------------------------------------------------------------------
+
+std::vector<std::vector<int8_t>> all_perms(int M)
+{
+    std::vector<int8_t> p(M);
+    for (int i = 0; i < M; ++i) p[i] = (int8_t)i;
+    std::vector<std::vector<int8_t>> out;
+    do {
+        out.push_back(p);
+    } while (std::next_permutation(p.begin(), p.end()));
+    return out;
+}
+
+i64 order_count(int M)
+{
+    if (M < 2 || M > 6) return -1;
+    i64 f = 1;
+    for (int i = 2; i < M; ++i) f *= i;  // (M-1)!
+    i64 c = 1;
+    for (int i = 0; i < M; ++i) c *= f;
+    return c;
+}
+
+namespace {
+
+// number of valid choices at stage s (0-based; stage 0 is the identity)
+i64 stage_choices(int M, int s)
+{
+    if (s == 0) return 1;
+    i64 f = 1;
+    for (int i = 2; i < M; ++i) f *= i;
+    return (i64)(M - s) * f;
+}
+
+}  // namespace
+
+Status order_at(int M, i64 index, int8_t *order)
+{
+    if (M < 2 || M > kMaxDims) return Status::err(-2, "M must be in [2, 5]");
+    if (!order) return Status::err(-1, "order is null");
+    i64 n = order_count(M);
+    if (index < 0 || index >= n) return Status::err(-1, "order index out of range");
+    auto perms = all_perms(M);
+    bool used[kMaxDims] = {};
+    for (int i = 0; i < M; ++i) order[i] = (int8_t)i;
+    used[M - 1] = true;
+    i64 rest = index;
+    for (int s = 1; s < M; ++s) {
+        i64 after = 1;
+        for (int s2 = s + 1; s2 < M; ++s2) after *= stage_choices(M, s2);
+        i64 digit = rest / after;
+        rest -= digit * after;
+        i64 seen = 0;
+        for (const auto &p : perms) {
+            if (used[p[M - 1]]) continue;
+            if (seen++ == digit) {
+                std::memcpy(order + s * M, p.data(), (size_t)M);
+                used[p[M - 1]] = true;
+                break;
+            }
+        }
+    }
+    return Status::ok();
+}
+
+Status order_index(int M, const int8_t *order, i64 *index)
+{
+    Status s = check_order(M, order);
+    if (!s) return s;
+    auto perms = all_perms(M);
+    bool used[kMaxDims] = {};
+    used[M - 1] = true;
+    i64 idx = 0;
+    for (int st = 1; st < M; ++st) {
+        i64 after = 1;
+        for (int s2 = st + 1; s2 < M; ++s2) after *= stage_choices(M, s2);
+        i64 digit = 0;
+        for (const auto &p : perms) {
+            if (used[p[M - 1]]) continue;
+            if (std::memcmp(p.data(), order + st * M, (size_t)M) == 0) break;
+            ++digit;
+        }
+        idx += digit * after;
+        used[order[st * M + M - 1]] = true;
+    }
+    *index = idx;
+    return Status::ok();
+}
+
+}  // namespace fftrw

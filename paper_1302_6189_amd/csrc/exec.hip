@@ -1,0 +1,497 @@
+// exec.hip -- plans and the Fig. 4 pipeline on one device (device half of the C ABI).
+//
+// Step t (t = 1..M) runs 1-D FFTs along the last axis of decomposition pi_t,
+// then transposes to pi_{t+1} (and after step M back to natural order).  The
+// N_p virtual processes own consecutive slices of the one buffer that holds
+// the array in the current layout, so the transpose is an on-device
+// permutation; the plan knows each transpose's analytic amount, and the
+// kernels can count it on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/fftrw.h"
+#include "decomp.hpp"
+#include "errors.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace fftrw {
+
+hipError_t launch_twiddles(void *out, int64_t n, bool fp64, hipStream_t s);
+hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in, void *out, double scale,
+                           hipStream_t s);
+hipError_t launch_xpose(const XposeDesc &d, size_t esz, const void *in, void *out, hipStream_t s);
+size_t xpose_lds_bytes(const XposeDesc &d, size_t esz);
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
+int staged_build(fft_plan_impl *pl, int t);
+int staged_run(fft_plan_impl *pl, int t, const void *in, void *out, hipStream_t s);
+void staged_free(fft_plan_impl *pl);
+
+namespace {
+
+int hip_fail(hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(FFTRW_E_DEVICE, m);
+}
+
+#define HIP_TRY(expr, what)                     \
+    do {                                        \
+        hipError_t _e = (expr);                 \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+bool smooth235(i64 n)
+{
+    if (n < 1) return false;
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+// Radix factorisation of a row length: powers of two as 8s with a 16, 4 or 2
+// to finish, then 3s and 5s.  Returns the number of passes.
+int factor_radices(i64 n, int *rad)
+{
+    int np = 0;
+    int e2 = 0;
+    while (n % 2 == 0) {
+        n /= 2;
+        ++e2;
+    }
+    int e3 = 0, e5 = 0;
+    while (n % 3 == 0) {
+        n /= 3;
+        ++e3;
+    }
+    while (n % 5 == 0) {
+        n /= 5;
+        ++e5;
+    }
+    // power-of-two part
+    int n8 = e2 / 3, rem = e2 % 3;
+    if (rem == 1 && n8 >= 1) {  // 2^(3m+1) = 16 * 8^(m-1)
+        rad[np++] = 16;
+        --n8;
+        rem = 0;
+    }
+    for (int i = 0; i < n8; ++i) rad[np++] = 8;
+    if (rem == 2) rad[np++] = 4;
+    if (rem == 1) rad[np++] = 2;
+    for (int i = 0; i < e3; ++i) rad[np++] = 3;
+    for (int i = 0; i < e5; ++i) rad[np++] = 5;
+    return np;
+}
+
+i64 pow2ceil(i64 x)
+{
+    i64 p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+int make_fft_desc(fft_plan_impl *pl, int t, FftDesc *d)
+{
+    const int ax = pl->order[t * pl->M + pl->M - 1];
+    const i64 N = pl->dims[ax];
+    if (!smooth235(N) || N > 4096)
+        return fail(FFTRW_E_SIZE, "row length " + std::to_string(N) + " must be 2^a 3^b 5^c and <= 4096");
+    std::memset(d, 0, sizeof(*d));
+    d->N = (int)N;
+    d->npass = factor_radices(N, d->radix);
+    const i64 elems = pl->esz == 8 ? 4096 : 2048;
+    i64 rw = 1;
+    while (rw * 2 <= 256 && rw * 2 * N <= elems) rw *= 2;
+    d->rows_per_wg = (int)rw;
+    d->lanes_per_row = (int)(256 / rw);
+    d->nrows = pl->T / N;
+    return FFTRW_OK;
+}
+
+int make_xpose_desc(fft_plan_impl *pl, const Layout &a, const Layout &b, const std::vector<i64> *mu,
+                    unsigned long long *counter, XposeDesc *d)
+{
+    const int M = pl->M;
+    std::memset(d, 0, sizeof(*d));
+    const int u = a.perm[M - 1], v = b.perm[M - 1];
+    if (u == v) return fail(FFTRW_E_ORDER, "consecutive decompositions share their last axis");
+    d->Nu = pl->dims[u];
+    d->Nv = pl->dims[v];
+    d->a_sv = a.stride[v];
+    d->b_su = b.stride[u];
+    // batch axes, innermost = smallest stride in A
+    int bat[3], nb = 0;
+    for (int ax = 0; ax < M; ++ax)
+        if (ax != u && ax != v) bat[nb++] = ax;
+    std::sort(bat, bat + nb, [&](int x, int y) { return a.stride[x] < a.stride[y]; });
+    d->nbat = nb;
+    d->nslices = 1;
+    int batpos[kMaxDims];
+    for (int i = 0; i < kMaxDims; ++i) batpos[i] = -1;
+    for (int i = 0; i < nb; ++i) {
+        d->bsize[i] = pl->dims[bat[i]];
+        d->ba[i] = a.stride[bat[i]];
+        d->bb[i] = b.stride[bat[i]];
+        d->nslices *= d->bsize[i];
+        batpos[bat[i]] = i;
+    }
+    d->TU = (int)std::min<i64>(64, pow2ceil(d->Nu));
+    d->TV = (int)std::min<i64>(64, pow2ceil(d->Nv));
+    const i64 elems = pl->esz == 8 ? 4096 : 2048;
+    i64 G = std::max<i64>(1, elems / ((i64)d->TU * d->TV));
+    G = std::min<i64>(G, 256);
+    G = std::min<i64>(G, d->nslices);
+    d->G = (int)G;
+    d->tiles_u = (d->Nu + d->TU - 1) / d->TU;
+    d->tiles_v = (d->Nv + d->TV - 1) / d->TV;
+    d->tiles_g = (d->nslices + G - 1) / G;
+    if (d->tiles_u * d->tiles_v * d->tiles_g >= (i64)0x7fffffff)
+        return fail(FFTRW_E_SIZE, "array too large for one transpose launch");
+    d->count = counter != nullptr;
+    d->counter = counter;
+    d->P = pl->P;
+    d->ka = a.k;
+    d->kb = b.k;
+    d->Ra = a.R;
+    d->Rb = b.R;
+    for (int j = 0; j < a.k; ++j) {
+        const int ax = a.perm[j];
+        d->srca[j] = ax == v ? 3 : batpos[ax];
+        i64 w = 1;
+        for (int i = j + 1; i < a.k; ++i) w *= a.pd[i];
+        d->wa[j] = w;
+    }
+    for (int j = 0; j < b.k; ++j) {
+        const int ax = b.perm[j];
+        d->srcb[j] = ax == u ? 4 : batpos[ax];
+        i64 w = 1;
+        for (int i = j + 1; i < b.k; ++i) w *= b.pd[i];
+        d->wb[j] = w;
+    }
+    (void)mu;
+    return FFTRW_OK;
+}
+
+void free_plan(fft_plan_impl *pl)
+{
+    if (!pl) return;
+    staged_free(pl);
+    for (void *p : pl->allocs) (void)hipFree(p);
+    pl->allocs.clear();
+    delete static_cast<fft_plan_s *>(pl);
+}
+
+int dev_alloc(fft_plan_impl *pl, void **p, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FFTRW_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    pl->allocs.push_back(*p);
+    pl->dev_bytes += bytes;
+    return FFTRW_OK;
+}
+
+int run_fft_step(fft_plan_impl *pl, int t, int dir, const void *in, void *out, double scale, hipStream_t s)
+{
+    HIP_TRY(launch_fft_rows(pl->fft[t], pl->esz == 16, dir, in, out, scale, s), "fft pass launch");
+    return FFTRW_OK;
+}
+
+int run_transpose(fft_plan_impl *pl, int t, const void *in, void *out, hipStream_t s)
+{
+    if (pl->flags & FFTRW_FLAG_STAGED) return staged_run(pl, t, in, out, s);
+    HIP_TRY(launch_xpose(pl->xp[t], pl->esz, in, out, s), "transpose launch");
+    return FFTRW_OK;
+}
+
+int run_pipeline(fft_plan_impl *pl, const void *in, void *out, hipStream_t s, int dir)
+{
+    const int M = pl->M;
+    const bool leave = (pl->flags & FFTRW_FLAG_LEAVE_PERMUTED) != 0;
+    const int nx = leave ? M - 1 : M;
+    if (pl->counters) HIP_TRY(launch_zero_u64(pl->counters, M, s), "counter reset");
+    void *b0 = (nx % 2 == 0) ? out : pl->work;
+    void *b1 = (b0 == out) ? pl->work : out;
+    void *cur = b0, *other = b1;
+    for (int t = 0; t < M; ++t) {
+        const double scale = (dir > 0 && t == M - 1) ? 1.0 / (double)pl->T : 1.0;
+        int rc = run_fft_step(pl, t, dir, t == 0 ? in : cur, cur, scale, s);
+        if (rc) return rc;
+        if (t < nx) {
+            rc = run_transpose(pl, t, cur, other, s);
+            if (rc) return rc;
+            std::swap(cur, other);
+        }
+    }
+    pl->executed = true;
+    return FFTRW_OK;
+}
+
+}  // namespace
+}  // namespace fftrw
+
+using namespace fftrw;
+
+extern "C" {
+
+int fft_plan(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8_t *order, int dtype,
+             int precision, unsigned flags)
+{
+    g_last_error.clear();
+    if (!plan) return fail(FFTRW_E_ARG, "plan must not be null");
+    *plan = nullptr;
+    Status st = check_dims(M, dims);
+    if (!st) return fail(st);
+    if (P < 1) return fail(FFTRW_E_ARG, "P must be >= 1");
+    if (dtype != FFTRW_C64 && dtype != FFTRW_C128) return fail(FFTRW_E_ARG, "unknown dtype");
+    if (precision < FFTRW_PREC_NATIVE || precision > FFTRW_PREC_SPLIT_BF16X3)
+        return fail(FFTRW_E_ARG, "unknown precision");
+    if (precision != FFTRW_PREC_NATIVE)
+        return fail(FFTRW_E_UNSUPPORTED, "split-precision MFMA passes are not built in this version");
+    if (flags & ~(unsigned)(FFTRW_FLAG_LEAVE_PERMUTED | FFTRW_FLAG_STAGED | FFTRW_FLAG_COUNT_MOVED |
+                            FFTRW_FLAG_OWN_MATCHED | FFTRW_FLAG_FUSED_FFT))
+        return fail(FFTRW_E_ARG, "unknown flag bits");
+    if (flags & FFTRW_FLAG_FUSED_FFT) return fail(FFTRW_E_UNSUPPORTED, "fused FFT+transpose not built yet");
+
+    fft_plan_s *pl = new (std::nothrow) fft_plan_s();
+    if (!pl) return fail(FFTRW_E_NOMEM, "out of host memory");
+    pl->M = M;
+    pl->P = P;
+    pl->dtype = dtype;
+    pl->precision = precision;
+    pl->flags = flags;
+    pl->ownership = (flags & FFTRW_FLAG_OWN_MATCHED) ? FFTRW_OWN_MATCHED : FFTRW_OWN_LITERAL;
+    pl->esz = dtype == FFTRW_C64 ? 8 : 16;
+    pl->T = 1;
+    for (int i = 0; i < M; ++i) {
+        pl->dims[i] = dims[i];
+        pl->T *= dims[i];
+    }
+    if (order) {
+        st = check_order(M, order);
+        if (!st) {
+            free_plan(pl);
+            return fail(st);
+        }
+        std::memcpy(pl->order, order, (size_t)(M * M));
+    } else {
+        int64_t bi = 0;
+        int rc = fft_order_search(M, dims, P, FFTRW_OWN_LITERAL, &bi, nullptr, nullptr, nullptr, nullptr,
+                                  nullptr, pl->order, nullptr);
+        if (rc) {
+            free_plan(pl);
+            return rc;
+        }
+    }
+    // layouts
+    int8_t ident[kMaxDims];
+    for (int i = 0; i < M; ++i) ident[i] = (int8_t)i;
+    for (int t = 0; t <= M; ++t) {
+        st = make_layout(M, dims, P, t < M ? pl->order + t * M : ident, &pl->lay[t]);
+        if (!st) {
+            free_plan(pl);
+            return fail(st);
+        }
+        if (t < M && pl->lay[t].row_split()) {
+            free_plan(pl);
+            return fail(FFTRW_E_ROWSPLIT, "P exceeds the rows available along some FFT axis (level M)");
+        }
+    }
+    // analytic amounts (and relabellings for the matched reading)
+    pl->analytic.assign(M, 0);
+    pl->mu.assign(M, {});
+    for (int t = 0; t < M; ++t) {
+        st = transpose_amount(pl->lay[t], pl->lay[t + 1], pl->ownership, &pl->analytic[t], &pl->mu[t]);
+        if (!st) {
+            free_plan(pl);
+            return fail(st);
+        }
+    }
+    int rc = hipGetDevice(&pl->device) == hipSuccess ? 0 : -1;
+    if (rc) {
+        free_plan(pl);
+        return fail(FFTRW_E_DEVICE, "no HIP device");
+    }
+    // FFT descriptors and twiddles
+    pl->fft.resize(M);
+    for (int t = 0; t < M; ++t) {
+        rc = make_fft_desc(pl, t, &pl->fft[t]);
+        if (rc) {
+            free_plan(pl);
+            return rc;
+        }
+        const int N = pl->fft[t].N;
+        if (!pl->twiddles.count(N)) {
+            void *tw = nullptr;
+            rc = dev_alloc(pl, &tw, (size_t)N * pl->esz);
+            if (rc) {
+                free_plan(pl);
+                return rc;
+            }
+            hipError_t e = launch_twiddles(tw, N, pl->esz == 16, nullptr);
+            if (e != hipSuccess) {
+                free_plan(pl);
+                return hip_fail(e, "twiddle generation");
+            }
+            pl->twiddles[N] = tw;
+        }
+        pl->fft[t].tw = pl->twiddles[N];
+    }
+    // workspace and counters
+    rc = dev_alloc(pl, &pl->work, (size_t)pl->T * pl->esz);
+    if (!rc && (flags & (FFTRW_FLAG_COUNT_MOVED | FFTRW_FLAG_STAGED)))
+        rc = dev_alloc(pl, (void **)&pl->counters, sizeof(unsigned long long) * (size_t)M);
+    if (rc) {
+        free_plan(pl);
+        return rc;
+    }
+    // relabelling tables on the device (matched reading)
+    std::vector<int *> mu_dev(M, nullptr);
+    if (pl->ownership == FFTRW_OWN_MATCHED) {
+        for (int t = 0; t < M; ++t) {
+            std::vector<int> m32(pl->mu[t].begin(), pl->mu[t].end());
+            void *p = nullptr;
+            rc = dev_alloc(pl, &p, sizeof(int) * m32.size());
+            if (!rc && hipMemcpy(p, m32.data(), sizeof(int) * m32.size(), hipMemcpyHostToDevice) != hipSuccess)
+                rc = fail(FFTRW_E_DEVICE, "copy of relabelling table failed");
+            if (rc) {
+                free_plan(pl);
+                return rc;
+            }
+            mu_dev[t] = (int *)p;
+        }
+    }
+    // transposes
+    pl->xp.resize(M);
+    pl->staged.resize(M);
+    for (int t = 0; t < M; ++t) {
+        unsigned long long *ctr = (flags & FFTRW_FLAG_COUNT_MOVED) ? pl->counters + t : nullptr;
+        rc = make_xpose_desc(pl, pl->lay[t], pl->lay[t + 1], &pl->mu[t], ctr, &pl->xp[t]);
+        if (rc) {
+            free_plan(pl);
+            return rc;
+        }
+        pl->xp[t].mu = mu_dev[t];
+        if (flags & FFTRW_FLAG_STAGED) {
+            rc = staged_build(pl, t);
+            if (rc) {
+                free_plan(pl);
+                return rc;
+            }
+        }
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        free_plan(pl);
+        return fail(FFTRW_E_DEVICE, "device error during plan creation");
+    }
+    *plan = pl;
+    return FFTRW_OK;
+}
+
+int fft_exec_fwd(fft_plan_t plan, const void *in, void *out, void *stream)
+{
+    g_last_error.clear();
+    if (!plan || !in || !out) return fail(FFTRW_E_ARG, "null plan or buffer");
+    return run_pipeline(plan, in, out, (hipStream_t)stream, -1);
+}
+
+int fft_exec_inv(fft_plan_t plan, const void *in, void *out, void *stream)
+{
+    g_last_error.clear();
+    if (!plan || !in || !out) return fail(FFTRW_E_ARG, "null plan or buffer");
+    return run_pipeline(plan, in, out, (hipStream_t)stream, +1);
+}
+
+int fft_exec_fft_step(fft_plan_t plan, int t, int direction, const void *in, void *out, void *stream)
+{
+    g_last_error.clear();
+    if (!plan || !in || !out) return fail(FFTRW_E_ARG, "null plan or buffer");
+    if (t < 0 || t >= plan->M) return fail(FFTRW_E_ARG, "step out of range");
+    if (direction != -1 && direction != 1) return fail(FFTRW_E_ARG, "direction must be -1 or +1");
+    return run_fft_step(plan, t, direction, in, out, 1.0, (hipStream_t)stream);
+}
+
+int fft_exec_transpose(fft_plan_t plan, int t, const void *in, void *out, void *stream)
+{
+    g_last_error.clear();
+    if (!plan || !in || !out) return fail(FFTRW_E_ARG, "null plan or buffer");
+    if (t < 0 || t >= plan->M) return fail(FFTRW_E_ARG, "transpose index out of range");
+    if (in == out) return fail(FFTRW_E_ARG, "a transpose cannot run in place");
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->counters) {
+        hipError_t e = launch_zero_u64(plan->counters + t, 1, s);
+        if (e != hipSuccess) return fail(FFTRW_E_DEVICE, hipGetErrorString(e));
+    }
+    int rc = run_transpose(plan, t, in, out, s);
+    if (!rc) plan->executed = true;
+    return rc;
+}
+
+int fft_plan_stats(fft_plan_t plan, int64_t *per_step, int64_t *moved)
+{
+    g_last_error.clear();
+    if (!plan) return fail(FFTRW_E_ARG, "null plan");
+    const int M = plan->M;
+    if (per_step)
+        for (int t = 0; t < M; ++t) per_step[t] = plan->analytic[t];
+    if (moved) {
+        for (int t = 0; t < M; ++t) moved[t] = -1;
+        if (plan->counters && plan->executed) {
+            std::vector<unsigned long long> h(M);
+            if (hipDeviceSynchronize() != hipSuccess)
+                return fail(FFTRW_E_DEVICE, "device error before reading counters");
+            if (hipMemcpy(h.data(), plan->counters, sizeof(unsigned long long) * M, hipMemcpyDeviceToHost) !=
+                hipSuccess)
+                return fail(FFTRW_E_DEVICE, "reading counters failed");
+            const bool leave = (plan->flags & FFTRW_FLAG_LEAVE_PERMUTED) != 0;
+            for (int t = 0; t < M; ++t)
+                if (!(leave && t == M - 1)) moved[t] = (int64_t)h[t];
+        }
+    }
+    return FFTRW_OK;
+}
+
+int fft_workspace_bytes(fft_plan_t plan, size_t *bytes)
+{
+    g_last_error.clear();
+    if (!plan || !bytes) return fail(FFTRW_E_ARG, "null argument");
+    *bytes = plan->dev_bytes;
+    return FFTRW_OK;
+}
+
+int fft_plan_describe(fft_plan_t plan, int8_t *order, char *text, size_t cap)
+{
+    g_last_error.clear();
+    if (!plan) return fail(FFTRW_E_ARG, "null plan");
+    if (order) std::memcpy(order, plan->order, (size_t)(plan->M * plan->M));
+    if (text && cap) {
+        std::string s;
+        for (int t = 0; t < plan->M; ++t) {
+            if (t) s += ";";
+            for (int p = 0; p < plan->fft[t].npass; ++p) {
+                if (p) s += "x";
+                s += std::to_string(plan->fft[t].radix[p]);
+            }
+        }
+        std::snprintf(text, cap, "%s", s.c_str());
+    }
+    return FFTRW_OK;
+}
+
+int fft_destroy(fft_plan_t plan)
+{
+    g_last_error.clear();
+    if (!plan) return FFTRW_OK;
+    free_plan(plan);
+    return FFTRW_OK;
+}
+
+}  // extern "C"

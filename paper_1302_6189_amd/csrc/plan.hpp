@@ -1,0 +1,60 @@
+// plan.hpp -- the execution plan behind fft_plan_t.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "decomp.hpp"
+#include "kernels.hpp"
+
+namespace fftrw {
+
+// Staged transpose tables (pack -> exchange -> unpack), see staged.hip.
+struct StagedStep {
+    int64_t nbox = 0;
+    void *boxes = nullptr;        // device BoxCopy[nbox]
+    void *pack_prefix = nullptr;  // device int64[nbox+1] tile prefix for pack
+    void *unpack_prefix = nullptr;
+    int64_t pack_tiles = 0, unpack_tiles = 0;
+    int64_t nseg = 0;
+    void *segs = nullptr;         // device SegCopy[nseg] (p != q only)
+    void *seg_prefix = nullptr;   // device int64[nseg+1] element prefix
+    int64_t seg_elems = 0;        // = the transpose's amount (points exchanged)
+};
+
+struct fft_plan_impl {
+    int M = 0;
+    i64 dims[kMaxDims] = {};
+    i64 P = 0;
+    int8_t order[kMaxDims * kMaxDims] = {};
+    int dtype = 1;
+    int precision = 0;
+    unsigned flags = 0;
+    int ownership = 0;
+    i64 T = 0;
+    size_t esz = 8;
+    int device = 0;
+
+    Layout lay[kMaxDims + 1];           // pi_1..pi_M, then natural
+    std::vector<FftDesc> fft;           // per step
+    std::vector<XposeDesc> xp;          // per transpose (M of them)
+    std::vector<i64> analytic;          // M: steps then return transpose
+    std::vector<std::vector<i64>> mu;   // per transpose relabelling (matched)
+    std::vector<StagedStep> staged;     // per transpose (STAGED flag)
+
+    // device memory
+    void *work = nullptr;
+    void *send = nullptr, *recv = nullptr;
+    unsigned long long *counters = nullptr;
+    std::vector<void *> allocs;
+    std::map<int, void *> twiddles;
+    size_t dev_bytes = 0;
+    bool executed = false;
+};
+
+}  // namespace fftrw
+
+struct fft_plan_s : fftrw::fft_plan_impl {};
