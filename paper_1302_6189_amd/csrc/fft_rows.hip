@@ -123,7 +123,7 @@ __device__ __forceinline__ void store_block(C *__restrict__ dst, const C *lds, i
 
 template <typename C, int DIR>
 __global__ void __launch_bounds__(kThreads)
-    fft_rows_kernel(const C *__restrict__ in, C *__restrict__ out, FftDesc d,
+    fft_rows_kernel(const C *in, C *out, FftDesc d,
                     typename RealOf<C>::type scale, int do_scale)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];

@@ -72,6 +72,11 @@ def lib():
     """Load libfftrw.so (built by ``paper_1302_6189_amd.build``); no fallback."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime and loads it by a different file name
+        # than the one this library links against; loading torch first makes
+        # both resolve to that single runtime (two runtimes in one process do
+        # not share devices).
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise FftrwError(E_DEVICE, f"{LIB_PATH} is missing: run `python -m paper_1302_6189_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
