@@ -225,6 +225,23 @@ int fft_exec_transpose(fft_plan_t plan, int t, const void *in, void *out,
  */
 int fft_plan_stats(fft_plan_t plan, int64_t *per_step, int64_t *moved);
 
+/*
+ * fft_plan_set_timing -- when enable != 0, every later exec records a HIP
+ * event on its stream after each stage (FFT step or transpose), so
+ * fft_plan_timings can report per-stage durations.  Creates the events on the
+ * current device; FFTRW_E_DEVICE if that fails.
+ */
+int fft_plan_set_timing(fft_plan_t plan, int enable);
+
+/*
+ * fft_plan_timings -- durations in milliseconds of the stages of the last
+ * exec with timing enabled, in launch order: FFT step 1, transpose 1, FFT
+ * step 2, ..., FFT step M, return transpose (absent with LEAVE_PERMUTED).
+ * ms: host array of capacity `cap`; *n receives the number of stages.
+ * Synchronises on the last event.
+ */
+int fft_plan_timings(fft_plan_t plan, float *ms, int cap, int *n);
+
 /* Device bytes the plan holds (workspace, staging, tables). */
 int fft_workspace_bytes(fft_plan_t plan, size_t *bytes);
 

@@ -23,6 +23,11 @@
 namespace fftrw {
 
 hipError_t launch_twiddles(void *out, int64_t n, bool fp64, hipStream_t s);
+bool pow2_supported(int N, bool fp64);
+void pow2_describe(int N, bool fp64, int *tw_count, int *radices, int *npass);
+hipError_t pow2_make_twiddles(int N, bool fp64, void *tw, hipStream_t s);
+hipError_t launch_fft_pow2(int N, bool fp64, const void *tw, int64_t nrows, int dir, const void *in, void *out,
+                           double scale, hipStream_t s);
 hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in, void *out, double scale,
                            hipStream_t s);
 hipError_t launch_xpose(const XposeDesc &d, size_t esz, const void *in, void *out, hipStream_t s);
@@ -103,7 +108,14 @@ int make_fft_desc(fft_plan_impl *pl, int t, FftDesc *d)
         return fail(FFTRW_E_SIZE, "row length " + std::to_string(N) + " must be 2^a 3^b 5^c and <= 4096");
     std::memset(d, 0, sizeof(*d));
     d->N = (int)N;
+    d->nrows = pl->T / N;
+    if (pow2_supported((int)N, pl->esz == 16)) {
+        d->pow2 = 1;
+        pow2_describe((int)N, pl->esz == 16, &d->tw_count, d->radix, &d->npass);
+        return FFTRW_OK;
+    }
     d->npass = factor_radices(N, d->radix);
+    d->tw_count = (int)N;
     const i64 elems = pl->esz == 8 ? 4096 : 2048;
     i64 rw = 1;
     while (rw * 2 <= 256 && rw * 2 * N <= elems) rw *= 2;
@@ -159,6 +171,7 @@ int make_xpose_desc(fft_plan_impl *pl, const Layout &a, const Layout &b, const s
     d->kb = b.k;
     d->Ra = a.R;
     d->Rb = b.R;
+    d->owner32 = (__int128)a.R * pl->P < ((__int128)1 << 32) && (__int128)b.R * pl->P < ((__int128)1 << 32);
     for (int j = 0; j < a.k; ++j) {
         const int ax = a.perm[j];
         d->srca[j] = ax == v ? 3 : batpos[ax];
@@ -180,6 +193,8 @@ int make_xpose_desc(fft_plan_impl *pl, const Layout &a, const Layout &b, const s
 void free_plan(fft_plan_impl *pl)
 {
     if (!pl) return;
+    for (hipEvent_t e : pl->events) (void)hipEventDestroy(e);
+    pl->events.clear();
     staged_free(pl);
     for (void *p : pl->allocs) (void)hipFree(p);
     pl->allocs.clear();
@@ -201,7 +216,12 @@ int dev_alloc(fft_plan_impl *pl, void **p, size_t bytes)
 
 int run_fft_step(fft_plan_impl *pl, int t, int dir, const void *in, void *out, double scale, hipStream_t s)
 {
-    HIP_TRY(launch_fft_rows(pl->fft[t], pl->esz == 16, dir, in, out, scale, s), "fft pass launch");
+    const FftDesc &d = pl->fft[t];
+    if (d.pow2) {
+        HIP_TRY(launch_fft_pow2(d.N, pl->esz == 16, d.tw, d.nrows, dir, in, out, scale, s), "fft pass launch");
+        return FFTRW_OK;
+    }
+    HIP_TRY(launch_fft_rows(d, pl->esz == 16, dir, in, out, scale, s), "fft pass launch");
     return FFTRW_OK;
 }
 
@@ -218,19 +238,27 @@ int run_pipeline(fft_plan_impl *pl, const void *in, void *out, hipStream_t s, in
     const bool leave = (pl->flags & FFTRW_FLAG_LEAVE_PERMUTED) != 0;
     const int nx = leave ? M - 1 : M;
     if (pl->counters) HIP_TRY(launch_zero_u64(pl->counters, M, s), "counter reset");
+    int nev = 0;
+    auto mark = [&]() -> int {
+        if (!pl->timing) return FFTRW_OK;
+        HIP_TRY(hipEventRecord(pl->events[nev++], s), "timing event");
+        return FFTRW_OK;
+    };
+    if (int rc = mark()) return rc;
     void *b0 = (nx % 2 == 0) ? out : pl->work;
     void *b1 = (b0 == out) ? pl->work : out;
     void *cur = b0, *other = b1;
     for (int t = 0; t < M; ++t) {
         const double scale = (dir > 0 && t == M - 1) ? 1.0 / (double)pl->T : 1.0;
         int rc = run_fft_step(pl, t, dir, t == 0 ? in : cur, cur, scale, s);
-        if (rc) return rc;
+        if (rc || (rc = mark())) return rc;
         if (t < nx) {
             rc = run_transpose(pl, t, cur, other, s);
-            if (rc) return rc;
+            if (rc || (rc = mark())) return rc;
             std::swap(cur, other);
         }
     }
+    pl->n_recorded = nev;
     pl->executed = true;
     return FFTRW_OK;
 }
@@ -331,12 +359,13 @@ int fft_plan(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8
         const int N = pl->fft[t].N;
         if (!pl->twiddles.count(N)) {
             void *tw = nullptr;
-            rc = dev_alloc(pl, &tw, (size_t)N * pl->esz);
+            rc = dev_alloc(pl, &tw, (size_t)std::max(1, pl->fft[t].tw_count) * pl->esz);
             if (rc) {
                 free_plan(pl);
                 return rc;
             }
-            hipError_t e = launch_twiddles(tw, N, pl->esz == 16, nullptr);
+            hipError_t e = pl->fft[t].pow2 ? pow2_make_twiddles(N, pl->esz == 16, tw, nullptr)
+                                           : launch_twiddles(tw, N, pl->esz == 16, nullptr);
             if (e != hipSuccess) {
                 free_plan(pl);
                 return hip_fail(e, "twiddle generation");
@@ -455,6 +484,38 @@ int fft_plan_stats(fft_plan_t plan, int64_t *per_step, int64_t *moved)
             for (int t = 0; t < M; ++t)
                 if (!(leave && t == M - 1)) moved[t] = (int64_t)h[t];
         }
+    }
+    return FFTRW_OK;
+}
+
+int fft_plan_set_timing(fft_plan_t plan, int enable)
+{
+    g_last_error.clear();
+    if (!plan) return fail(FFTRW_E_ARG, "null plan");
+    if (enable && plan->events.empty()) {
+        plan->events.resize(2 * plan->M + 1);
+        for (hipEvent_t &e : plan->events)
+            if (hipEventCreate(&e) != hipSuccess) return fail(FFTRW_E_DEVICE, "hipEventCreate failed");
+    }
+    plan->timing = enable != 0;
+    plan->n_recorded = 0;
+    return FFTRW_OK;
+}
+
+int fft_plan_timings(fft_plan_t plan, float *ms, int cap, int *n)
+{
+    g_last_error.clear();
+    if (!plan || !n) return fail(FFTRW_E_ARG, "null argument");
+    const int stages = plan->n_recorded > 0 ? plan->n_recorded - 1 : 0;
+    *n = stages;
+    if (stages == 0) return FFTRW_OK;
+    if (hipEventSynchronize(plan->events[stages]) != hipSuccess)
+        return fail(FFTRW_E_DEVICE, "waiting for timing events failed");
+    for (int i = 0; i < stages && i < cap; ++i) {
+        float v = 0.f;
+        if (hipEventElapsedTime(&v, plan->events[i], plan->events[i + 1]) != hipSuccess)
+            return fail(FFTRW_E_DEVICE, "hipEventElapsedTime failed");
+        if (ms) ms[i] = v;
     }
     return FFTRW_OK;
 }

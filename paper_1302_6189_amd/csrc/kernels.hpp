@@ -17,7 +17,10 @@ struct FftDesc {
     int rows_per_wg;   // RW: rows held in LDS by one work-group (power of two)
     int lanes_per_row; // 256 / RW threads cooperate on one row
     int64_t nrows;
-    const void *tw;    // forward twiddles w_N^e, e = 0..N-1 (float2 or double2)
+    const void *tw;    // forward twiddles w_N^e, e = 0..N-1 (float2 or double2),
+                       // or the per-pass table of the power-of-two kernel
+    int pow2;          // 1: compile-time power-of-two kernel (fft_pow2.hip)
+    int tw_count;      // entries in the twiddle table
 };
 
 // Fused permutation of the whole array from layout A to layout B with a
@@ -40,6 +43,7 @@ struct XposeDesc {
     int srca[5], srcb[5];    // for each leading axis: 0..2 batch index, 3 = v, 4 = u
     int64_t wa[5], wb[5];    // row-index weights of the leading axes
     int64_t Ra, Rb, P;
+    int owner32;             // (r+1) P - 1 fits in 32 bits for both layouts
     const int *mu;           // relabelling of A's ranges (nullable = identity)
     unsigned long long *counter;
 };

@@ -53,6 +53,11 @@ struct fft_plan_impl {
     std::map<int, void *> twiddles;
     size_t dev_bytes = 0;
     bool executed = false;
+
+    // per-stage timing events (fft_plan_set_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> events;  // stage boundaries of the last exec
+    int n_recorded = 0;
 };
 
 }  // namespace fftrw

@@ -5,7 +5,8 @@
 // permutation is a tiled 2-D transpose between u (fastest axis of A) and v
 // (fastest axis of B), batched over the other M-2 axes.  A work-group reads a
 // TU x TV tile (times G batch slices) along u, transposes it through LDS and
-// writes it along v, so both sides are coalesced.
+// writes it along v, so both sides are coalesced; with an even u (v) size a
+// thread moves two neighbouring values per 16-byte access.
 //
 // Owner counting: virtual process p owns a contiguous range of rows over the
 // first k axes of its decomposition (Eqs. (13)-(15)).  The first k axes of A
@@ -23,104 +24,175 @@ namespace fftrw {
 
 constexpr int kMaxG = 256;
 
-__device__ __forceinline__ int64_t owner_of_row(int64_t r, int64_t P, int64_t R)
+typedef float xf4 __attribute__((ext_vector_type(4)));
+typedef float xf2 __attribute__((ext_vector_type(2)));
+typedef double xd2 __attribute__((ext_vector_type(2)));
+
+template <typename C> __device__ __forceinline__ C xld(const C *p)
 {
+    if constexpr (sizeof(C) == 8) {
+        xf2 w = __builtin_nontemporal_load(reinterpret_cast<const xf2 *>(p));
+        return mk<C>(w.x, w.y);
+    } else {
+        xd2 w = __builtin_nontemporal_load(reinterpret_cast<const xd2 *>(p));
+        return mk<C>(w.x, w.y);
+    }
+}
+template <typename C> __device__ __forceinline__ void xst(C *p, C v)
+{
+    if constexpr (sizeof(C) == 8) {
+        xf2 w = {v.x, v.y};
+        __builtin_nontemporal_store(w, reinterpret_cast<xf2 *>(p));
+    } else {
+        xd2 w = {v.x, v.y};
+        __builtin_nontemporal_store(w, reinterpret_cast<xd2 *>(p));
+    }
+}
+
+__device__ __forceinline__ int64_t owner_of_row(int64_t r, int64_t P, int64_t R, bool narrow)
+{
+    if (narrow) return (int64_t)(((uint32_t)(r + 1) * (uint32_t)P - 1u) / (uint32_t)R);
     return ((r + 1) * P - 1) / R;
 }
 
-template <typename C>
+// coordinates of batch slice s (innermost batch axis first) and its bases
+__device__ __forceinline__ void slice_coords(const XposeDesc &d, int64_t s, int *c, int64_t *ab, int64_t *bb)
+{
+    int64_t a = 0, b = 0;
+    for (int i = 0; i < d.nbat; ++i) {
+        const int64_t q = s / d.bsize[i];
+        const int64_t ci = s - q * d.bsize[i];
+        s = q;
+        c[i] = (int)ci;
+        a += ci * d.ba[i];
+        b += ci * d.bb[i];
+    }
+    *ab = a;
+    *bb = b;
+}
+
+template <typename C, int VU, int VV>
 __global__ void __launch_bounds__(kThreads) xpose_kernel(const C *__restrict__ in, C *__restrict__ out, XposeDesc d)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *tile = reinterpret_cast<C *>(smem_raw);
-    __shared__ int64_t abase[kMaxG], bbase[kMaxG];
-    __shared__ int bcoord[kMaxG][3];
     __shared__ int moved_wg;
 
     const int TU = d.TU, TV = d.TV;
     const int ldt = TU + 1;
-    int64_t t = blockIdx.x;
-    const int64_t tu = t % d.tiles_u;
-    t /= d.tiles_u;
-    const int64_t tv = t % d.tiles_v;
-    const int64_t tg = t / d.tiles_v;
-    const int64_t u0 = tu * TU, v0 = tv * TV, g0 = tg * d.G;
+    uint32_t t = blockIdx.x;
+    const uint32_t tu = t % (uint32_t)d.tiles_u;
+    t /= (uint32_t)d.tiles_u;
+    const uint32_t tv = t % (uint32_t)d.tiles_v;
+    const uint32_t tg = t / (uint32_t)d.tiles_v;
+    const int64_t u0 = (int64_t)tu * TU, v0 = (int64_t)tv * TV, g0 = (int64_t)tg * d.G;
     const int nu = (int)min<int64_t>(TU, d.Nu - u0);
     const int nv = (int)min<int64_t>(TV, d.Nv - v0);
     const int ng = (int)min<int64_t>(d.G, d.nslices - g0);
 
-    for (int g = threadIdx.x; g < ng; g += kThreads) {
-        int64_t s = g0 + g, ab = 0, bb = 0;
-        for (int i = 0; i < d.nbat; ++i) {
-            int64_t c = s % d.bsize[i];
-            s /= d.bsize[i];
-            ab += c * d.ba[i];
-            bb += c * d.bb[i];
-            bcoord[g][i] = (int)c;
-        }
-        abase[g] = ab;
-        bbase[g] = bb;
-    }
-    if (threadIdx.x == 0) moved_wg = 0;
-    __syncthreads();
-
-    // load: rows (g, v) of TU contiguous u-values
-    {
-        const int tx = threadIdx.x % TU;
-        const int ty = threadIdx.x / TU;
-        const int ystep = kThreads / TU;
-        const int nrow = ng * nv;
-        for (int r = ty; r < nrow; r += ystep) {
-            const int g = r / nv;
-            const int iv = r - g * nv;
-            if (tx < nu) tile[(g * TV + iv) * ldt + tx] = in[abase[g] + (v0 + iv) * d.a_sv + u0 + tx];
-        }
-    }
-    __syncthreads();
-
-    // owner vectors of this tile (counting mode)
-    int *own_a = nullptr, *own_b = nullptr;
+    int *own_a = reinterpret_cast<int *>(tile + (size_t)d.G * TV * ldt);
+    int *own_b = own_a + d.G * TV;
     if (d.count) {
-        own_a = reinterpret_cast<int *>(tile + (size_t)d.G * TV * ldt);
-        own_b = own_a + d.G * TV;
+        if (threadIdx.x == 0) moved_wg = 0;
+        // owner vectors: A's over (slice, v), B's over (slice, u)
+        const bool narrow = d.owner32 != 0;
         for (int i = threadIdx.x; i < ng * nv; i += kThreads) {
             const int g = i / nv, iv = i - g * nv;
+            int c[3];
+            int64_t ab, bb;
+            slice_coords(d, g0 + g, c, &ab, &bb);
             int64_t r = 0;
             for (int j = 0; j < d.ka; ++j) {
                 const int src = d.srca[j];
-                const int64_t c = src == 3 ? v0 + iv : (int64_t)bcoord[g][src];
-                r += c * d.wa[j];
+                r += (src == 3 ? v0 + iv : (int64_t)c[src]) * d.wa[j];
             }
-            int64_t o = owner_of_row(r, d.P, d.Ra);
+            int64_t o = owner_of_row(r, d.P, d.Ra, narrow);
             if (d.mu) o = d.mu[o];
             own_a[g * TV + iv] = (int)o;
         }
         for (int i = threadIdx.x; i < ng * nu; i += kThreads) {
             const int g = i / nu, iu = i - g * nu;
+            int c[3];
+            int64_t ab, bb;
+            slice_coords(d, g0 + g, c, &ab, &bb);
             int64_t r = 0;
             for (int j = 0; j < d.kb; ++j) {
                 const int src = d.srcb[j];
-                const int64_t c = src == 4 ? u0 + iu : (int64_t)bcoord[g][src];
-                r += c * d.wb[j];
+                r += (src == 4 ? u0 + iu : (int64_t)c[src]) * d.wb[j];
             }
-            own_b[g * TU + iu] = (int)owner_of_row(r, d.P, d.Rb);
+            own_b[g * TU + iu] = (int)owner_of_row(r, d.P, d.Rb, narrow);
         }
-        __syncthreads();
     }
 
-    // store: rows (g, u) of TV contiguous v-values
+    // load: rows (g, v) of contiguous u-values
+    {
+        const int per_row = TU / VU;
+        const int tx = threadIdx.x % per_row;
+        const int ty = threadIdx.x / per_row;
+        const int ystep = kThreads / per_row;
+        const int nrow = ng * nv;
+        int gcur = -1;
+        int64_t abase = 0;
+        for (int r = ty; r < nrow; r += ystep) {
+            const int g = r / nv;
+            const int iv = r - g * nv;
+            if (g != gcur) {
+                int c[3];
+                int64_t bb;
+                slice_coords(d, g0 + g, c, &abase, &bb);
+                gcur = g;
+            }
+            const int iu = tx * VU;
+            if (iu < nu) {
+                const C *p = in + abase + (v0 + iv) * d.a_sv + u0 + iu;
+                C *trow = tile + (g * TV + iv) * ldt + iu;
+                if constexpr (VU == 2) {
+                    xf4 w = __builtin_nontemporal_load(reinterpret_cast<const xf4 *>(p));
+                    trow[0] = mk<C>(w.x, w.y);
+                    trow[1] = mk<C>(w.z, w.w);
+                } else {
+                    trow[0] = xld(p);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // store: rows (g, u) of contiguous v-values
     int moved = 0;
     {
-        const int tx = threadIdx.x % TV;
-        const int ty = threadIdx.x / TV;
-        const int ystep = kThreads / TV;
+        const int per_row = TV / VV;
+        const int tx = threadIdx.x % per_row;
+        const int ty = threadIdx.x / per_row;
+        const int ystep = kThreads / per_row;
         const int nrow = ng * nu;
+        int gcur = -1;
+        int64_t bbase = 0;
         for (int r = ty; r < nrow; r += ystep) {
             const int g = r / nu;
             const int iu = r - g * nu;
-            if (tx < nv) {
-                out[bbase[g] + (u0 + iu) * d.b_su + v0 + tx] = tile[(g * TV + tx) * ldt + iu];
-                if (d.count) moved += own_a[g * TV + tx] != own_b[g * TU + iu];
+            if (g != gcur) {
+                int c[3];
+                int64_t ab;
+                slice_coords(d, g0 + g, c, &ab, &bbase);
+                gcur = g;
+            }
+            const int iv = tx * VV;
+            if (iv < nv) {
+                C *p = out + bbase + (u0 + iu) * d.b_su + v0 + iv;
+                const C *tcol = tile + (g * TV + iv) * ldt + iu;
+                if constexpr (VV == 2) {
+                    const C a0 = tcol[0], a1 = tcol[ldt];
+                    xf4 w = {a0.x, a0.y, a1.x, a1.y};
+                    __builtin_nontemporal_store(w, reinterpret_cast<xf4 *>(p));
+                } else {
+                    xst(p, tcol[0]);
+                }
+                if (d.count) {
+                    const int ob = own_b[g * TU + iu];
+                    moved += own_a[g * TV + iv] != ob;
+                    if (VV == 2) moved += own_a[g * TV + iv + 1] != ob;
+                }
             }
         }
     }
@@ -145,10 +217,24 @@ hipError_t launch_xpose(const XposeDesc &d, size_t esz, const void *in, void *ou
     if (nblk <= 0) return hipSuccess;
     const size_t lds = xpose_lds_bytes(d, esz);
     dim3 grid((unsigned)nblk), block(kThreads);
-    if (esz == 8)
-        hipLaunchKernelGGL(xpose_kernel<float2>, grid, block, lds, s, (const float2 *)in, (float2 *)out, d);
-    else
-        hipLaunchKernelGGL(xpose_kernel<double2>, grid, block, lds, s, (const double2 *)in, (double2 *)out, d);
+    // 16-byte accesses for complex64 along an even fast axis
+    const bool vu = esz == 8 && d.Nu % 2 == 0 && d.TU >= 2;
+    const bool vv = esz == 8 && d.Nv % 2 == 0 && d.TV >= 2;
+    if (esz == 8) {
+        const float2 *i = (const float2 *)in;
+        float2 *o = (float2 *)out;
+        if (vu && vv)
+            hipLaunchKernelGGL((xpose_kernel<float2, 2, 2>), grid, block, lds, s, i, o, d);
+        else if (vu)
+            hipLaunchKernelGGL((xpose_kernel<float2, 2, 1>), grid, block, lds, s, i, o, d);
+        else if (vv)
+            hipLaunchKernelGGL((xpose_kernel<float2, 1, 2>), grid, block, lds, s, i, o, d);
+        else
+            hipLaunchKernelGGL((xpose_kernel<float2, 1, 1>), grid, block, lds, s, i, o, d);
+    } else {
+        hipLaunchKernelGGL((xpose_kernel<double2, 1, 1>), grid, block, lds, s, (const double2 *)in,
+                           (double2 *)out, d);
+    }
     return hipGetLastError();
 }
 

@@ -61,6 +61,9 @@ _SIGNATURES = {
     "fft_exec_transpose": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     "fft_plan_stats": (ctypes.c_int, [_vp, _i64p, _i64p]),
     "fft_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "fft_plan_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "fft_plan_timings": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int)]),
     "fft_plan_describe": (ctypes.c_int, [_vp, _i8p, ctypes.c_char_p, ctypes.c_size_t]),
     "fft_destroy": (ctypes.c_int, [_vp]),
     "fft_last_error": (ctypes.c_char_p, []),
@@ -262,6 +265,16 @@ class Plan:
         a, m = (ctypes.c_int64 * self.M)(), (ctypes.c_int64 * self.M)()
         _check(lib().fft_plan_stats(self._h, a, m))
         return list(a), list(m)
+
+    def set_timing(self, enable=True):
+        _check(lib().fft_plan_set_timing(self._h, 1 if enable else 0))
+
+    def timings(self):
+        """Per-stage durations (ms) of the last exec: FFT 1, transpose 1, ..."""
+        buf = (ctypes.c_float * (2 * self.M + 1))()
+        n = ctypes.c_int()
+        _check(lib().fft_plan_timings(self._h, buf, 2 * self.M + 1, ctypes.byref(n)))
+        return list(buf)[:n.value]
 
     def workspace_bytes(self):
         b = ctypes.c_size_t()
