@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--P", type=int, default=4096)
     ap.add_argument("--order", default="best", help="best, worst or a canonical order index")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="one forward transform plus a plain 1 GiB device copy, for counter runs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -113,6 +115,16 @@ def main():
     y = torch.empty_like(x)
     z = torch.empty_like(x)
     stream = torch.cuda.current_stream()
+
+    if args.pmc_probe:
+        # counters are read per dispatch: one forward transform, then a plain
+        # copy of the same 1 GiB as the calibration for the HBM byte counters
+        plan.exec_fwd(x, y, stream)
+        torch.cuda.synchronize()
+        z.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": "done", "bytes_per_copy": 2 * T * 8}), flush=True)
+        return
 
     for _ in range(args.warmup):
         plan.exec_fwd(x, y, stream)
@@ -149,7 +161,7 @@ def main():
     xp_ms = stage_ms[1::2]
     bytes_per_launch = 2 * T * 8  # every point read once and written once
     kernels = {
-        "fft_rows_kernel": {"avg_ms": sum(fft_ms) / len(fft_ms), "launches_per_transform": len(fft_ms)},
+        "fft_pow2_kernel": {"avg_ms": sum(fft_ms) / len(fft_ms), "launches_per_transform": len(fft_ms)},
         "xpose_kernel": {"avg_ms": sum(xp_ms) / len(xp_ms), "launches_per_transform": len(xp_ms)},
     }
     for k in kernels.values():
