@@ -28,6 +28,8 @@ void pow2_describe(int N, bool fp64, int *tw_count, int *radices, int *npass);
 hipError_t pow2_make_twiddles(int N, bool fp64, void *tw, hipStream_t s);
 hipError_t launch_fft_pow2(int N, bool fp64, const void *tw, int64_t nrows, int dir, const void *in, void *out,
                            double scale, hipStream_t s);
+hipError_t launch_fft256_mfma(int precision, int dir, const void *tw256, int64_t nrows, const void *in, void *out,
+                              double scale, hipStream_t s);
 hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in, void *out, double scale,
                            hipStream_t s);
 hipError_t launch_xpose(const XposeDesc &d, size_t esz, const void *in, void *out, hipStream_t s);
@@ -109,6 +111,14 @@ int make_fft_desc(fft_plan_impl *pl, int t, FftDesc *d)
     std::memset(d, 0, sizeof(*d));
     d->N = (int)N;
     d->nrows = pl->T / N;
+    if (pl->precision != FFTRW_PREC_NATIVE && N == 256) {
+        // two radix-16 DFT contractions on MFMA, generic 256-entry twiddle table
+        d->mfma = pl->precision;
+        d->npass = 2;
+        d->radix[0] = d->radix[1] = 16;
+        d->tw_count = 256;
+        return FFTRW_OK;
+    }
     if (pow2_supported((int)N, pl->esz == 16)) {
         d->pow2 = 1;
         pow2_describe((int)N, pl->esz == 16, &d->tw_count, d->radix, &d->npass);
@@ -217,6 +227,10 @@ int dev_alloc(fft_plan_impl *pl, void **p, size_t bytes)
 int run_fft_step(fft_plan_impl *pl, int t, int dir, const void *in, void *out, double scale, hipStream_t s)
 {
     const FftDesc &d = pl->fft[t];
+    if (d.mfma) {
+        HIP_TRY(launch_fft256_mfma(d.mfma, dir, d.tw, d.nrows, in, out, scale, s), "mfma fft pass launch");
+        return FFTRW_OK;
+    }
     if (d.pow2) {
         HIP_TRY(launch_fft_pow2(d.N, pl->esz == 16, d.tw, d.nrows, dir, in, out, scale, s), "fft pass launch");
         return FFTRW_OK;
@@ -282,8 +296,8 @@ int fft_plan(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8
     if (dtype != FFTRW_C64 && dtype != FFTRW_C128) return fail(FFTRW_E_ARG, "unknown dtype");
     if (precision < FFTRW_PREC_NATIVE || precision > FFTRW_PREC_SPLIT_BF16X3)
         return fail(FFTRW_E_ARG, "unknown precision");
-    if (precision != FFTRW_PREC_NATIVE)
-        return fail(FFTRW_E_UNSUPPORTED, "split-precision MFMA passes are not built in this version");
+    if (precision != FFTRW_PREC_NATIVE && dtype != FFTRW_C64)
+        return fail(FFTRW_E_UNSUPPORTED, "the split-precision MFMA form computes complex64 data");
     if (flags & ~(unsigned)(FFTRW_FLAG_LEAVE_PERMUTED | FFTRW_FLAG_STAGED | FFTRW_FLAG_COUNT_MOVED |
                             FFTRW_FLAG_OWN_MATCHED | FFTRW_FLAG_FUSED_FFT))
         return fail(FFTRW_E_ARG, "unknown flag bits");
@@ -364,8 +378,8 @@ int fft_plan(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8
                 free_plan(pl);
                 return rc;
             }
-            hipError_t e = pl->fft[t].pow2 ? pow2_make_twiddles(N, pl->esz == 16, tw, nullptr)
-                                           : launch_twiddles(tw, N, pl->esz == 16, nullptr);
+            hipError_t e = (pl->fft[t].pow2 && !pl->fft[t].mfma) ? pow2_make_twiddles(N, pl->esz == 16, tw, nullptr)
+                                                                 : launch_twiddles(tw, N, pl->esz == 16, nullptr);
             if (e != hipSuccess) {
                 free_plan(pl);
                 return hip_fail(e, "twiddle generation");
@@ -537,6 +551,7 @@ int fft_plan_describe(fft_plan_t plan, int8_t *order, char *text, size_t cap)
         std::string s;
         for (int t = 0; t < plan->M; ++t) {
             if (t) s += ";";
+            if (plan->fft[t].mfma) s += "mfma:";
             for (int p = 0; p < plan->fft[t].npass; ++p) {
                 if (p) s += "x";
                 s += std::to_string(plan->fft[t].radix[p]);

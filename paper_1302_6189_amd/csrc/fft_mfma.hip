@@ -1,0 +1,228 @@
+// fft_mfma.hip -- 256-point row FFTs as radix-16 DFT contractions on MFMA.
+//
+// The precision form of a step of Fig. 4: with N = 256 = 16 x 16 and the row
+// x viewed as the 16 x 16 matrix X[n1][n2] = x[16 n1 + n2], Eq. (1) factors as
+//     Y  = F16 X                        (16-point DFTs of the 16 columns)
+//     Y'[k1][n2] = Y[k1][n2] w_256^{n2 k1}
+//     Z  = F16 Y'^T,   xbar[16 k2 + k1] = Z[k2][k1],
+// F16[k][n] = w_16^{kn}.  Both products are 16 x 16 complex matrices times
+// 16 x 16 complex matrices, run in real form on one wave as
+//     Re = [Fr | -Fi] [Br; Bi],   Im = [Fi | Fr] [Br; Bi]
+// (16x32 by 32x16, one v_mfma_f32_16x16x32 each).  Operands are split into a
+// high and a low half-precision part (FP16, or BF16 with two or three parts)
+// after a power-of-two scaling per column (one 16-point input vector), and
+// the partial products are accumulated in FP32:
+//     two parts:   A_h B_h + A_h B_l + A_l B_h
+//     three parts: the six products whose parts' orders sum to at most 2.
+// The twiddles between the stages are applied in FP32 from a table computed
+// in FP64; F16 itself is generated in FP64 on the device.
+#include <hip/hip_runtime.h>
+
+#include "cplx.hpp"
+#include "kernels.hpp"
+
+namespace fftrw {
+
+typedef _Float16 mh8 __attribute__((ext_vector_type(8)));
+typedef __bf16 mb8 __attribute__((ext_vector_type(8)));
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef float mf2v __attribute__((ext_vector_type(2)));
+
+enum { kPrecF16 = 1, kPrecBF16 = 2, kPrecBF16x3 = 3 };
+
+template <int PREC> struct Parts;
+template <> struct Parts<kPrecF16> {
+    using V = mh8;
+    static constexpr int n = 2;
+    static __device__ __forceinline__ float round(float x) { return (float)(_Float16)x; }
+    static __device__ __forceinline__ mf4 mma(V a, V b, mf4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ void set(V &v, int i, float x) { v[i] = (_Float16)x; }
+};
+template <int PREC> struct PartsBF16 {
+    using V = mb8;
+    static constexpr int n = PREC == kPrecBF16 ? 2 : 3;
+    static __device__ __forceinline__ float round(float x) { return (float)(__bf16)x; }
+    static __device__ __forceinline__ mf4 mma(V a, V b, mf4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ void set(V &v, int i, float x) { v[i] = (__bf16)x; }
+};
+template <> struct Parts<kPrecBF16> : PartsBF16<kPrecBF16> {};
+template <> struct Parts<kPrecBF16x3> : PartsBF16<kPrecBF16x3> {};
+
+// split 8 values into PT::n parts (x = p0 + p1 [+ p2] up to rounding of the last)
+template <class PT>
+__device__ __forceinline__ void split8(const float *x, typename PT::V *p)
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        float r = x[i];
+#pragma unroll
+        for (int q = 0; q < PT::n; ++q) {
+            const float h = PT::round(r);
+            PT::set(p[q], i, h);
+            r -= h;
+        }
+    }
+}
+
+// C += A B over the split parts, smallest terms first
+template <class PT>
+__device__ __forceinline__ mf4 split_product(const typename PT::V *a, const typename PT::V *b)
+{
+    mf4 acc = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (PT::n == 3) {
+        acc = PT::mma(a[1], b[1], acc);
+        acc = PT::mma(a[2], b[0], acc);
+        acc = PT::mma(a[0], b[2], acc);
+    }
+    acc = PT::mma(a[1], b[0], acc);
+    acc = PT::mma(a[0], b[1], acc);
+    acc = PT::mma(a[0], b[0], acc);
+    return acc;
+}
+
+// power-of-two exponent s such that max|x| * 2^s lies in [2^14, 2^15)
+__device__ __forceinline__ int column_exponent(const float *b, int lane)
+{
+    float m = 0.f;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) m = fmaxf(m, fabsf(b[v]));
+    // the 32 reals of a column sit in lanes c, c+16, c+32, c+48
+    m = fmaxf(m, __shfl_xor(m, 16));
+    m = fmaxf(m, __shfl_xor(m, 32));
+    if (!(m > 0.f)) return 0;
+    int e;
+    (void)frexpf(m, &e);
+    return 15 - e;
+}
+
+template <int PREC, int DIR>
+__global__ void __launch_bounds__(kThreads)
+    fft256_mfma_kernel(const float2 *in, float2 *out, int64_t nrows, const float2 *__restrict__ tw256, float scale,
+                       int do_scale)
+{
+    using PT = Parts<PREC>;
+    using V = typename PT::V;
+    __shared__ float2 ybuf[kThreads / 64][16 * 17];  // one padded 16 x 16 block per wave
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;   // lane group 0..3
+    const int c = lane & 15;   // column (A: row) index
+    float2 *yb = ybuf[wave];
+
+    // A operands [Fr | -Fi] and [Fi | Fr], lane holds row c, k = 8g + v
+    V a1[PT::n], a2[PT::n];
+    {
+        float f1[8], f2[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int k = 8 * g + v;
+            const int kk = k & 15;
+            double s, co;
+            sincospi(2.0 * (double)((c * kk) & 15) / 16.0, &s, &co);
+            const float fr = (float)co, fi = (float)(DIR * s);
+            f1[v] = k < 16 ? fr : -fi;
+            f2[v] = k < 16 ? fi : fr;
+        }
+        split8<PT>(f1, a1);
+        split8<PT>(f2, a2);
+    }
+
+    const int64_t row = (int64_t)blockIdx.x * (kThreads / 64) + wave;
+    if (row >= nrows) return;  // whole wave exits together; no block barrier follows
+    const float2 *x = in + row * 256;
+    float2 *y = out + row * 256;
+    const bool im = g >= 2;
+    const int n1base = 8 * (g & 1);
+
+    // ---- stage 1: B[k][c] = x[16 n1 + c], k = 8g + v ----------------------------
+    float b[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        mf2v e = __builtin_nontemporal_load(reinterpret_cast<const mf2v *>(x + 16 * (n1base + v) + c));
+        b[v] = im ? e.y : e.x;
+    }
+    int s1 = column_exponent(b, lane);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) b[v] = ldexpf(b[v], s1);
+    V bp[PT::n];
+    split8<PT>(b, bp);
+    mf4 cr = split_product<PT>(a1, bp);
+    mf4 ci = split_product<PT>(a2, bp);
+
+    // unscale, twiddle w_256^{n2 k1} (k1 = 4g + v, n2 = c) and stage through LDS
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int k1 = 4 * g + v;
+        float2 w = tw256[c * k1];
+        float re = ldexpf(cr[v], -s1), imv = ldexpf(ci[v], -s1);
+        float2 t = DIR < 0 ? cmul(mk<float2>(re, imv), w) : cmulc(mk<float2>(re, imv), w);
+        yb[k1 * 17 + c] = t;
+    }
+    // the LDS block is private to this wave: order its writes before the reads
+    // of other lanes with a wave-level barrier (no work-group barrier, so
+    // waves past the last row may already have exited)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // ---- stage 2: B2[n2][k1] = Y'[k1][n2], column k1 = c ------------------------
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const float2 e = yb[c * 17 + n1base + v];
+        b[v] = im ? e.y : e.x;
+    }
+    int s2 = column_exponent(b, lane);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) b[v] = ldexpf(b[v], s2);
+    split8<PT>(b, bp);
+    cr = split_product<PT>(a1, bp);
+    ci = split_product<PT>(a2, bp);
+
+    // Z[k2][k1] with k2 = 4g + v, k1 = c lands at y[16 k2 + k1]
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int k2 = 4 * g + v;
+        float re = ldexpf(cr[v], -s2), imv = ldexpf(ci[v], -s2);
+        if (do_scale) {
+            re *= scale;
+            imv *= scale;
+        }
+        mf2v o = {re, imv};
+        __builtin_nontemporal_store(o, reinterpret_cast<mf2v *>(y + 16 * k2 + c));
+    }
+}
+
+hipError_t launch_fft256_mfma(int precision, int dir, const void *tw256, int64_t nrows, const void *in, void *out,
+                              double scale, hipStream_t s)
+{
+    const int64_t nblk = (nrows + 3) / 4;
+    if (nblk <= 0) return hipSuccess;
+    const int ds = scale != 1.0;
+    dim3 grid((unsigned)nblk), block(kThreads);
+    const float2 *i = (const float2 *)in;
+    float2 *o = (float2 *)out;
+    const float2 *t = (const float2 *)tw256;
+    const float sc = (float)scale;
+#define FFTRW_LAUNCH(P, D) \
+    hipLaunchKernelGGL((fft256_mfma_kernel<P, D>), grid, block, 0, s, i, o, nrows, t, sc, ds)
+    if (precision == kPrecF16) {
+        if (dir < 0) FFTRW_LAUNCH(kPrecF16, -1); else FFTRW_LAUNCH(kPrecF16, 1);
+    } else if (precision == kPrecBF16) {
+        if (dir < 0) FFTRW_LAUNCH(kPrecBF16, -1); else FFTRW_LAUNCH(kPrecBF16, 1);
+    } else if (precision == kPrecBF16x3) {
+        if (dir < 0) FFTRW_LAUNCH(kPrecBF16x3, -1); else FFTRW_LAUNCH(kPrecBF16x3, 1);
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef FFTRW_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace fftrw
