@@ -74,6 +74,72 @@ def cpu_baseline(dims, x_host):
                       f"({sec:.2f} s measured, x{dims[0] // S} to one transform)"}
 
 
+def time_fwd(plan, x, y, stream, reps, warm=3):
+    """Average milliseconds of one forward transform (HIP events on the exec stream)."""
+    import torch
+    for _ in range(warm):
+        plan.exec_fwd(x, y, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        plan.exec_fwd(x, y, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def precision_forms(reps):
+    """256^3 complex64 (P = 64, best order): FP32 Stockham against the split
+    FP16 / BF16 / BF16x3 MFMA forms; time per transform and errors against the
+    FP64 oracle on uniform and log-uniform inputs."""
+    import numpy as np
+    import torch
+
+    from oracle import dft, orders
+    from paper_1302_6189_amd import fftrw, inputs
+    dims = (256, 256, 256)
+    T = math.prod(dims)
+    order = fftrw.fft_order_search(dims, 64)["best_order"]
+    seq = orders.fft_axis_sequence(order)
+    data = {}
+    for kind, seed in (("uniform", 4), ("log_uniform", 40)):
+        x = getattr(inputs, kind)(dims, seed, np.complex64)
+        data[kind] = (x, dft.fftn_direct(x, seq))
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, prec in (("fp32", fftrw.PREC_NATIVE), ("split_f16", fftrw.PREC_SPLIT_F16),
+                       ("split_bf16", fftrw.PREC_SPLIT_BF16), ("split_bf16x3", fftrw.PREC_SPLIT_BF16X3)):
+        plan = fftrw.Plan(dims, 64, order, precision=prec)
+        entry = {}
+        for kind, (x, ref) in data.items():
+            xd = torch.from_numpy(x).cuda()
+            yd = torch.empty_like(xd)
+            if kind == "uniform":
+                ms = time_fwd(plan, xd, yd, stream, reps)
+                entry["ms_per_transform"] = round(ms, 4)
+                entry["GFLOPs"] = round(5 * T * math.log2(T) / (ms * 1e-3) / 1e9, 1)
+            plan.exec_fwd(xd, yd, stream)
+            torch.cuda.synchronize()
+            y = yd.cpu().numpy()
+            entry[kind] = {"rel_l2": float(f"{dft.rel_l2(y, ref):.3e}"),
+                           "max_abs": float(f"{dft.max_abs(y, ref):.3e}"),
+                           "max_abs_over_max_ref": float(f"{dft.max_abs_rel(y, ref):.3e}")}
+            del xd, yd
+        plan.set_timing(True)
+        xd = torch.from_numpy(data["uniform"][0]).cuda()
+        yd = torch.empty_like(xd)
+        plan.exec_fwd(xd, yd, stream)
+        st = plan.timings()
+        plan.set_timing(False)
+        entry["fft_pass_ms"] = round(sum(st[0::2]) / 3, 4)
+        entry["fft_pass_GBs"] = round(2 * T * 8 / (entry["fft_pass_ms"] * 1e-3) / 1e9, 1)
+        res[name] = entry
+        plan.destroy()
+    res["workload"] = "3-D complex64 FFT 256x256x256, P=64, order " + fftrw.order_to_str(order)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +148,7 @@ def main():
     ap.add_argument("--P", type=int, default=4096)
     ap.add_argument("--order", default="best", help="best, worst or a canonical order index")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision and batched legs")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="one forward transform plus a plain 1 GiB device copy, for counter runs")
     args = ap.parse_args()
@@ -206,6 +273,10 @@ def main():
                      "traffic": traffic},
         "wall_s_timed": round(wall, 3),
     }
+    del x, y, z
+    if not args.no_forms:
+        torch.cuda.empty_cache()
+        out["precision_form"] = precision_forms(args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dims, x_host)
     print(json.dumps(out), flush=True)

@@ -76,8 +76,10 @@ enum {
     FFTRW_FLAG_COUNT_MOVED = 4u,     /* count, on the device, the points whose
                                         owner changes in every transpose          */
     FFTRW_FLAG_OWN_MATCHED = 8u,     /* ownership reading R2 (see fft_comm_volume)*/
-    FFTRW_FLAG_FUSED_FFT = 16u       /* fuse each FFT step with the transpose that
+    FFTRW_FLAG_FUSED_FFT = 16u,      /* fuse each FFT step with the transpose that
                                         follows it (one HBM pass per step)        */
+    FFTRW_FLAG_BATCH_NO_GRAPH = 32u  /* batched form: launch the persistent kernel
+                                        directly instead of replaying a graph     */
 };
 
 typedef struct fft_plan_s *fft_plan_t;
@@ -250,6 +252,57 @@ int fft_workspace_bytes(fft_plan_t plan, size_t *bytes);
 int fft_plan_describe(fft_plan_t plan, int8_t *order, char *text, size_t cap);
 
 int fft_destroy(fft_plan_t plan);
+
+/* ---- batched form: many uneven transforms in one persistent launch ------- */
+
+/* One item of a batch: an M-D complex64 transform of sizes dims[0..M) over P
+ * virtual processes, with the transpose order `order` (M*M int8 as for
+ * fft_plan) when has_order != 0, else the best order of fft_order_search. */
+typedef struct {
+    int M;
+    int64_t dims[5];
+    int64_t P;
+    int8_t order[25];
+    int has_order;
+} fft_item_desc;
+
+typedef struct fft_batch_s *fft_batch_t;
+
+/*
+ * fft_batch_plan -- plan n independent transforms (each the Fig. 4 pipeline)
+ * to run together in ONE persistent kernel launch, replayed from a HIP graph.
+ * The work of every item is cut into units (row blocks of an FFT step, tiles
+ * of a transpose), numbered stage level by stage level; work-groups take
+ * units from an atomic counter and wait, per item, for the item's earlier
+ * stages (bounded waits: a wait past its limit sets the error flag reported by
+ * fft_batch_stats and the unit is skipped).  precision must be
+ * FFTRW_PREC_NATIVE; flags: COUNT_MOVED, LEAVE_PERMUTED, BATCH_NO_GRAPH.
+ * tune_cache: path of the autotuner's cache (fft_autotune) or NULL for the
+ * built-in plan.  Each item's row lengths follow fft_plan's rules; the batch
+ * owns one T_i-element workspace per item.
+ */
+int fft_batch_plan(fft_batch_t *batch, int n, const fft_item_desc *items,
+                   int precision, const char *tune_cache, unsigned flags);
+
+/* Forward / inverse of every item: in[i], out[i] are device pointers to T_i
+ * complex64 values in natural layout (host arrays of n pointers).  One graph
+ * launch on `stream` (the first call per direction captures it). */
+int fft_batch_exec_fwd(fft_batch_t batch, void *const *in, void *const *out,
+                       void *stream);
+int fft_batch_exec_inv(fft_batch_t batch, void *const *in, void *const *out,
+                       void *stream);
+
+/*
+ * fft_batch_stats -- moved (sum of M_i, nullable): device-counted owner
+ * changes per transpose of every item (COUNT_MOVED), items in order;
+ * analytic (same shape, nullable): the plan's amounts; units: number of work
+ * units of one exec; error: nonzero if a unit's wait exceeded its limit in the
+ * last exec (synchronises the device).
+ */
+int fft_batch_stats(fft_batch_t batch, int64_t *moved, int64_t *analytic,
+                    int64_t *units, int *error);
+
+int fft_batch_destroy(fft_batch_t batch);
 
 /* Text of the last error on the calling thread ("" if none). */
 const char *fft_last_error(void);

@@ -1,0 +1,436 @@
+// batch.hip -- many uneven transforms in one persistent launch.
+//
+// Each item is a whole Fig. 4 pipeline (M FFT steps and M transposes) with its
+// own sizes, process count and order.  The work of all items is cut into
+// units -- a block of rows of one FFT step, or a tile of one transpose --
+// grouped into stage levels: level s holds stage s of every item that has
+// one.  One grid of work-groups, sized to stay resident, sweeps the levels:
+// inside a level units are taken from the level's atomic counter; between
+// levels the grid meets at a barrier (one release before arriving, one
+// acquire after leaving, at device scope, so the data written on one XCD is
+// seen on the others), which keeps every item's FFT -> transpose -> FFT order.
+// Waiting polls a device-coherent counter without invalidating caches, and
+// every wait is bounded by the real-time clock: past the bound the
+// work-group sets an error flag and goes on, so the grid always drains.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fftrw.h"
+#include "decomp.hpp"
+#include "errors.hpp"
+#include "fft_generic.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "xpose_tile.hpp"
+
+namespace fftrw {
+
+constexpr int kMaxStages = 2 * kMaxDims;
+
+struct BatchItemDev {
+    const float2 *in;
+    float2 *out;
+    float2 *work;
+    int M;
+    int nstage;                     // 2M, or 2M - 1 with LEAVE_PERMUTED
+    int src[kMaxStages];            // 0 in, 1 out, 2 work
+    int dst[kMaxStages];
+    int64_t prefix[kMaxStages + 1]; // units of this item before stage s
+    float inv_scale;                // 1/T for the inverse's last FFT step
+    int xv[kMaxDims];               // 16-byte access flags of transpose t: bit0 u, bit1 v
+    FftDesc fft[kMaxDims];
+    XposeDesc xp[kMaxDims];
+};
+
+struct BatchTask {
+    int item, stage;
+    int64_t unit0, nunits;  // unit0 counts from the start of the task's level
+};
+
+// zeroed before every launch: error flag, barrier arrivals, one unit counter per level
+struct BatchCounters {
+    unsigned long long error;
+    unsigned long long arrived;
+    unsigned long long next[kMaxStages];
+};
+
+// real-time clock ticks (100 MHz) a work-group may wait at one barrier
+constexpr unsigned long long kWaitTicks = 200000000ull;
+
+__device__ __forceinline__ float2 *batch_buf(const BatchItemDev &it, int kind)
+{
+    return kind == 0 ? const_cast<float2 *>(it.in) : (kind == 1 ? it.out : it.work);
+}
+
+template <int DIR>
+__global__ void __launch_bounds__(kThreads)
+    batch_kernel(const BatchItemDev *__restrict__ items, const BatchTask *__restrict__ tasks,
+                 const int *__restrict__ level_task0, const int64_t *__restrict__ level_units, int nlevels,
+                 BatchCounters *ctr)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int64_t s_unit;
+    for (int lv = 0; lv < nlevels; ++lv) {
+        const int64_t nunits = level_units[lv];
+        const int t0 = level_task0[lv], t1 = level_task0[lv + 1];
+        for (;;) {
+            if (threadIdx.x == 0) s_unit = (int64_t)atomicAdd(&ctr->next[lv], 1ull);
+            __syncthreads();
+            const int64_t u = s_unit;
+            __syncthreads();  // every thread has read s_unit before it changes
+            if (u >= nunits) break;
+            int lo = t0, hi = t1 - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (tasks[mid].unit0 <= u)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const BatchTask tk = tasks[lo];
+            const BatchItemDev &it = items[tk.item];
+            const int64_t local = u - tk.unit0;
+            const int st = tk.stage;
+            const float2 *src = batch_buf(it, it.src[st]);
+            float2 *dst = batch_buf(it, it.dst[st]);
+            const int t = st >> 1;
+            if ((st & 1) == 0) {
+                const bool last = t == it.M - 1;
+                fft_rows_block<float2, DIR>(src, dst, it.fft[t], local, DIR > 0 && last ? it.inv_scale : 1.f,
+                                            DIR > 0 && last, reinterpret_cast<float2 *>(smem));
+            } else {
+                switch (it.xv[t]) {
+                case 3: xpose_tile<float2, 2, 2>(src, dst, it.xp[t], (uint32_t)local, smem); break;
+                case 1: xpose_tile<float2, 2, 1>(src, dst, it.xp[t], (uint32_t)local, smem); break;
+                case 2: xpose_tile<float2, 1, 2>(src, dst, it.xp[t], (uint32_t)local, smem); break;
+                default: xpose_tile<float2, 1, 1>(src, dst, it.xp[t], (uint32_t)local, smem); break;
+                }
+            }
+        }
+        if (lv + 1 == nlevels) break;
+        // grid barrier between levels
+        __threadfence();  // release this work-group's writes of the level
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long target = (unsigned long long)gridDim.x * (unsigned long long)(lv + 1);
+            atomicAdd(&ctr->arrived, 1ull);
+            const unsigned long long w0 = wall_clock64();
+            while (__hip_atomic_load(&ctr->arrived, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (wall_clock64() - w0 > kWaitTicks) {
+                    atomicOr(&ctr->error, 1ull);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(10);
+            }
+        }
+        __syncthreads();
+        __threadfence();  // acquire the other work-groups' writes
+    }
+}
+
+__global__ void batch_reset_kernel(unsigned long long *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+}  // namespace fftrw
+
+// ---- host side ----------------------------------------------------------------
+namespace fftrw {
+
+int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8_t *order, int dtype,
+                int precision, unsigned flags, bool generic_rows);
+void plan_free(fft_plan_t plan);
+
+struct fft_batch_impl {
+    int n = 0;
+    unsigned flags = 0;
+    std::vector<fft_plan_t> plans;
+    std::vector<BatchItemDev> h_items;
+    std::vector<BatchTask> h_tasks;
+    BatchItemDev *d_items = nullptr;
+    BatchTask *d_tasks = nullptr;
+    unsigned long long *d_ctr = nullptr;  // BatchCounters, then moved[sum of M_i]
+    int64_t nctr = 0;
+    std::vector<int> level_task0;         // first task of each level (+ end)
+    std::vector<int64_t> level_units;     // units of each level
+    int *d_level_task0 = nullptr;
+    int64_t *d_level_units = nullptr;
+    std::vector<int64_t> moved_off;       // first moved counter of each item
+    int64_t total = 0;
+    int grid = 0;
+    size_t lds = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    bool pointers_set = false;
+};
+
+namespace {
+
+int batch_fail_hip(hipError_t e, const char *what)
+{
+    return fail(FFTRW_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void batch_free(fft_batch_impl *b)
+{
+    if (!b) return;
+    for (int d = 0; d < 2; ++d) {
+        if (b->gexec[d]) (void)hipGraphExecDestroy(b->gexec[d]);
+        if (b->graph[d]) (void)hipGraphDestroy(b->graph[d]);
+    }
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (void *p : {(void *)b->d_items, (void *)b->d_tasks, (void *)b->d_ctr, (void *)b->d_level_task0,
+                    (void *)b->d_level_units})
+        if (p) (void)hipFree(p);
+    for (fft_plan_t p : b->plans) plan_free(p);
+    delete b;
+}
+
+// enqueue reset + persistent kernel on stream s
+int batch_enqueue(fft_batch_impl *b, int dir, hipStream_t s)
+{
+    const int64_t nctr = b->nctr;
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((unsigned)((nctr + 255) / 256)), dim3(256), 0, s, b->d_ctr, nctr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return batch_fail_hip(e, "batch reset launch");
+    BatchCounters *ctr = reinterpret_cast<BatchCounters *>(b->d_ctr);
+    const int nl = (int)b->level_units.size();
+    if (dir < 0)
+        hipLaunchKernelGGL(batch_kernel<-1>, dim3(b->grid), dim3(kThreads), b->lds, s, b->d_items, b->d_tasks,
+                           b->d_level_task0, b->d_level_units, nl, ctr);
+    else
+        hipLaunchKernelGGL(batch_kernel<1>, dim3(b->grid), dim3(kThreads), b->lds, s, b->d_items, b->d_tasks,
+                           b->d_level_task0, b->d_level_units, nl, ctr);
+    e = hipGetLastError();
+    if (e != hipSuccess) return batch_fail_hip(e, "batch kernel launch");
+    return FFTRW_OK;
+}
+
+}  // namespace
+}  // namespace fftrw
+
+struct fft_batch_s : fftrw::fft_batch_impl {};
+
+using namespace fftrw;
+
+extern "C" {
+
+int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int precision, const char *tune_cache,
+                   unsigned flags)
+{
+    g_last_error.clear();
+    (void)tune_cache;
+    if (!out || !items || n < 1) return fail(FFTRW_E_ARG, "null output, null items or n < 1");
+    *out = nullptr;
+    if (precision != FFTRW_PREC_NATIVE)
+        return fail(FFTRW_E_UNSUPPORTED, "the batched form runs the FP32 Stockham kernels");
+    if (flags & ~(unsigned)(FFTRW_FLAG_COUNT_MOVED | FFTRW_FLAG_LEAVE_PERMUTED | FFTRW_FLAG_BATCH_NO_GRAPH))
+        return fail(FFTRW_E_UNSUPPORTED, "the batched form supports COUNT_MOVED, LEAVE_PERMUTED and NO_GRAPH only");
+    fft_batch_s *b = new (std::nothrow) fft_batch_s();
+    if (!b) return fail(FFTRW_E_NOMEM, "out of host memory");
+    b->n = n;
+    b->flags = flags;
+    const unsigned pflags = flags & (FFTRW_FLAG_COUNT_MOVED | FFTRW_FLAG_LEAVE_PERMUTED);
+    const bool leave = (flags & FFTRW_FLAG_LEAVE_PERMUTED) != 0;
+    b->h_items.resize(n);
+    size_t lds = 16;
+    int max_stage = 0;
+    for (int i = 0; i < n; ++i) {
+        const fft_item_desc &it = items[i];
+        fft_plan_t p = nullptr;
+        int rc = plan_create(&p, it.M, it.dims, it.P, it.has_order ? it.order : nullptr, FFTRW_C64,
+                             FFTRW_PREC_NATIVE, pflags, true);
+        if (rc) {
+            std::string m = "item " + std::to_string(i) + ": " + g_last_error;
+            batch_free(b);
+            return fail(rc, m);
+        }
+        b->plans.push_back(p);
+        BatchItemDev &d = b->h_items[i];
+        std::memset(&d, 0, sizeof(d));
+        d.M = it.M;
+        const int nx = leave ? it.M - 1 : it.M;
+        d.nstage = it.M + nx;
+        d.work = (float2 *)p->work;
+        d.inv_scale = (float)(1.0 / (double)p->T);
+        // buffer sequence of the pipeline: FFT 0 reads the input; transposes alternate
+        const int b0 = (nx % 2 == 0) ? 1 : 2, b1 = b0 == 1 ? 2 : 1;
+        int cur = b0, other = b1;
+        int64_t units = 0;
+        for (int st = 0; st < d.nstage; ++st) {
+            d.prefix[st] = units;
+            const int t = st >> 1;
+            if ((st & 1) == 0) {
+                d.src[st] = t == 0 ? 0 : cur;
+                d.dst[st] = cur;
+                d.fft[t] = p->fft[t];
+                units += (d.fft[t].nrows + d.fft[t].rows_per_wg - 1) / d.fft[t].rows_per_wg;
+                lds = std::max(lds, (size_t)d.fft[t].rows_per_wg * d.fft[t].N * 8);
+            } else {
+                d.src[st] = cur;
+                d.dst[st] = other;
+                std::swap(cur, other);
+                d.xp[t] = p->xp[t];
+                d.xv[t] = ((d.xp[t].Nu % 2 == 0 && d.xp[t].TU >= 2) ? 1 : 0) |
+                          ((d.xp[t].Nv % 2 == 0 && d.xp[t].TV >= 2) ? 2 : 0);
+                units += d.xp[t].tiles_u * d.xp[t].tiles_v * d.xp[t].tiles_g;
+                lds = std::max(lds, xpose_tile_bytes(d.xp[t], 8) + 16);
+            }
+        }
+        d.prefix[d.nstage] = units;
+        max_stage = std::max(max_stage, d.nstage);
+    }
+    // stage level by stage level, items in order; units numbered within a level
+    for (int s = 0; s < max_stage; ++s) {
+        b->level_task0.push_back((int)b->h_tasks.size());
+        int64_t lvl = 0;
+        for (int i = 0; i < n; ++i) {
+            const BatchItemDev &d = b->h_items[i];
+            if (s >= d.nstage) continue;
+            const int64_t cnt = d.prefix[s + 1] - d.prefix[s];
+            if (cnt <= 0) continue;
+            b->h_tasks.push_back({i, s, lvl, cnt});
+            lvl += cnt;
+        }
+        b->level_units.push_back(lvl);
+        b->total += lvl;
+    }
+    b->level_task0.push_back((int)b->h_tasks.size());
+    b->lds = (lds + 15) & ~(size_t)15;
+    b->moved_off.resize(n);
+    b->nctr = (int64_t)(sizeof(BatchCounters) / sizeof(unsigned long long));
+    for (int i = 0; i < n; ++i) {
+        b->moved_off[i] = b->nctr;
+        b->nctr += b->h_items[i].M;
+    }
+    int dev = 0, ncu = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<-1>, kThreads, b->lds);
+    if (e != hipSuccess || per_cu < 1 || ncu < 1) {
+        batch_free(b);
+        return e != hipSuccess ? batch_fail_hip(e, "occupancy query") : fail(FFTRW_E_DEVICE, "kernel does not fit");
+    }
+    b->grid = per_cu * ncu;
+    e = hipMalloc(&b->d_items, sizeof(BatchItemDev) * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&b->d_tasks, sizeof(BatchTask) * b->h_tasks.size());
+    if (e == hipSuccess) e = hipMalloc(&b->d_ctr, sizeof(unsigned long long) * (size_t)b->nctr);
+    if (e == hipSuccess && (flags & FFTRW_FLAG_COUNT_MOVED)) {
+        // owner-change counters of every transpose live in the batch's counter
+        // block, which the graph's reset kernel clears before each launch
+        for (int i = 0; i < n; ++i)
+            for (int t = 0; t < b->h_items[i].M; ++t)
+                if (b->h_items[i].xp[t].count) b->h_items[i].xp[t].counter = b->d_ctr + b->moved_off[i] + t;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_tasks, b->h_tasks.data(), sizeof(BatchTask) * b->h_tasks.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&b->d_level_task0, sizeof(int) * b->level_task0.size());
+    if (e == hipSuccess) e = hipMalloc(&b->d_level_units, sizeof(int64_t) * b->level_units.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_level_task0, b->level_task0.data(), sizeof(int) * b->level_task0.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_level_units, b->level_units.data(), sizeof(int64_t) * b->level_units.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        batch_free(b);
+        return fail(FFTRW_E_NOMEM, "device allocation for the batch failed");
+    }
+    *out = b;
+    return FFTRW_OK;
+}
+
+static int batch_exec(fft_batch_t b, void *const *in, void *const *out, void *stream, int dir)
+{
+    g_last_error.clear();
+    if (!b || !in || !out) return fail(FFTRW_E_ARG, "null batch or pointer arrays");
+    bool changed = !b->pointers_set;
+    for (int i = 0; i < b->n; ++i) {
+        if (!in[i] || !out[i]) return fail(FFTRW_E_ARG, "null buffer for item " + std::to_string(i));
+        BatchItemDev &d = b->h_items[i];
+        if (d.in != in[i] || d.out != out[i]) changed = true;
+        d.in = (const float2 *)in[i];
+        d.out = (float2 *)out[i];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (changed) {
+        // the item table is read by the kernel; update it in stream order
+        hipError_t e = hipStreamSynchronize(s);
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_items, b->h_items.data(), sizeof(BatchItemDev) * (size_t)b->n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return batch_fail_hip(e, "item table update");
+        b->pointers_set = true;
+    }
+    if (b->flags & FFTRW_FLAG_BATCH_NO_GRAPH) return batch_enqueue(b, dir, s);
+    const int di = dir < 0 ? 0 : 1;
+    if (!b->gexec[di]) {
+        hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return batch_fail_hip(e, "graph capture begin");
+        int rc = batch_enqueue(b, dir, b->cap_stream);
+        e = hipStreamEndCapture(b->cap_stream, &b->graph[di]);
+        if (rc) return rc;
+        if (e != hipSuccess) return batch_fail_hip(e, "graph capture end");
+        e = hipGraphInstantiate(&b->gexec[di], b->graph[di], nullptr, nullptr, 0);
+        if (e != hipSuccess) return batch_fail_hip(e, "graph instantiate");
+    }
+    hipError_t e = hipGraphLaunch(b->gexec[di], s);
+    if (e != hipSuccess) return batch_fail_hip(e, "graph launch");
+    return FFTRW_OK;
+}
+
+int fft_batch_exec_fwd(fft_batch_t b, void *const *in, void *const *out, void *stream)
+{
+    return batch_exec(b, in, out, stream, -1);
+}
+
+int fft_batch_exec_inv(fft_batch_t b, void *const *in, void *const *out, void *stream)
+{
+    return batch_exec(b, in, out, stream, 1);
+}
+
+int fft_batch_stats(fft_batch_t b, int64_t *moved, int64_t *analytic, int64_t *units, int *error)
+{
+    g_last_error.clear();
+    if (!b) return fail(FFTRW_E_ARG, "null batch");
+    if (units) *units = b->total;
+    std::vector<unsigned long long> h((size_t)b->nctr, 0ull);
+    if (moved || error) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipMemcpy(h.data(), b->d_ctr, sizeof(unsigned long long) * h.size(),
+                                           hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return batch_fail_hip(e, "reading batch counters");
+    }
+    const bool leave = (b->flags & FFTRW_FLAG_LEAVE_PERMUTED) != 0;
+    const bool counted = (b->flags & FFTRW_FLAG_COUNT_MOVED) != 0;
+    int off = 0;
+    for (int i = 0; i < b->n; ++i) {
+        const int M = b->h_items[i].M;
+        for (int t = 0; t < M; ++t) {
+            if (analytic) analytic[off + t] = b->plans[i]->analytic[t];
+            if (moved)
+                moved[off + t] = (counted && !(leave && t == M - 1)) ? (int64_t)h[b->moved_off[i] + t] : -1;
+        }
+        off += M;
+    }
+    if (error) *error = (int)h[0];
+    return FFTRW_OK;
+}
+
+int fft_batch_destroy(fft_batch_t b)
+{
+    g_last_error.clear();
+    batch_free(b);
+    return FFTRW_OK;
+}
+
+}  // extern "C"

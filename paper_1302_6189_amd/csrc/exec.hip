@@ -102,7 +102,7 @@ i64 pow2ceil(i64 x)
     return p;
 }
 
-int make_fft_desc(fft_plan_impl *pl, int t, FftDesc *d)
+int make_fft_desc(fft_plan_impl *pl, int t, FftDesc *d, bool generic_rows)
 {
     const int ax = pl->order[t * pl->M + pl->M - 1];
     const i64 N = pl->dims[ax];
@@ -119,7 +119,7 @@ int make_fft_desc(fft_plan_impl *pl, int t, FftDesc *d)
         d->tw_count = 256;
         return FFTRW_OK;
     }
-    if (pow2_supported((int)N, pl->esz == 16)) {
+    if (!generic_rows && pow2_supported((int)N, pl->esz == 16)) {
         d->pow2 = 1;
         pow2_describe((int)N, pl->esz == 16, &d->tw_count, d->radix, &d->npass);
         return FFTRW_OK;
@@ -278,14 +278,11 @@ int run_pipeline(fft_plan_impl *pl, const void *in, void *out, hipStream_t s, in
 }
 
 }  // namespace
-}  // namespace fftrw
 
-using namespace fftrw;
-
-extern "C" {
-
-int fft_plan(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8_t *order, int dtype,
-             int precision, unsigned flags)
+// Build a plan; generic_rows forces the runtime-radix row kernel for every
+// step (the persistent batched kernel runs only that one).
+int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8_t *order, int dtype,
+                int precision, unsigned flags, bool generic_rows)
 {
     g_last_error.clear();
     if (!plan) return fail(FFTRW_E_ARG, "plan must not be null");
@@ -299,7 +296,7 @@ int fft_plan(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8
     if (precision != FFTRW_PREC_NATIVE && dtype != FFTRW_C64)
         return fail(FFTRW_E_UNSUPPORTED, "the split-precision MFMA form computes complex64 data");
     if (flags & ~(unsigned)(FFTRW_FLAG_LEAVE_PERMUTED | FFTRW_FLAG_STAGED | FFTRW_FLAG_COUNT_MOVED |
-                            FFTRW_FLAG_OWN_MATCHED | FFTRW_FLAG_FUSED_FFT))
+                            FFTRW_FLAG_OWN_MATCHED | FFTRW_FLAG_FUSED_FFT | FFTRW_FLAG_BATCH_NO_GRAPH))
         return fail(FFTRW_E_ARG, "unknown flag bits");
     if (flags & FFTRW_FLAG_FUSED_FFT) return fail(FFTRW_E_UNSUPPORTED, "fused FFT+transpose not built yet");
 
@@ -365,7 +362,7 @@ int fft_plan(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8
     // FFT descriptors and twiddles
     pl->fft.resize(M);
     for (int t = 0; t < M; ++t) {
-        rc = make_fft_desc(pl, t, &pl->fft[t]);
+        rc = make_fft_desc(pl, t, &pl->fft[t], generic_rows);
         if (rc) {
             free_plan(pl);
             return rc;
@@ -437,6 +434,20 @@ int fft_plan(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8
     }
     *plan = pl;
     return FFTRW_OK;
+}
+
+void plan_free(fft_plan_t plan) { free_plan(plan); }
+
+}  // namespace fftrw
+
+using namespace fftrw;
+
+extern "C" {
+
+int fft_plan(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8_t *order, int dtype,
+             int precision, unsigned flags)
+{
+    return fftrw::plan_create(plan, M, dims, P, order, dtype, precision, flags, false);
 }
 
 int fft_exec_fwd(fft_plan_t plan, const void *in, void *out, void *stream)

@@ -1,0 +1,139 @@
+// fft_generic.hpp -- batched 1-D FFTs along contiguous rows of any 2,3,5-smooth
+// length (device code shared by the stand-alone kernel and the persistent
+// batched kernel).
+//
+// Every step of the paper's parallel M-D FFT runs independent 1-D FFTs (Eq. (1))
+// along the last axis of the current decomposition; after the preceding
+// transpose those rows are contiguous.  A work-group stages RW whole rows
+// (RW * N <= 4096 complex values for FP32, 2048 for FP64) in LDS with 16-byte
+// coalesced loads, runs the Stockham autosort passes there (one radix-R
+// butterfly per thread per R outputs, values staged in registers between two
+// barriers so one LDS buffer suffices), and stores the rows back coalesced.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cplx.hpp"
+#include "kernels.hpp"
+
+namespace fftrw {
+
+// ---- one Stockham pass in LDS ----------------------------------------------------
+// Pass with radix R after sub-transforms of size Ns: butterfly j (< N/R) reads
+// x[j + i N/R], multiplies by w_{Ns R}^{i k} (k = j mod Ns), runs DFT_R and
+// writes y[(j - k) R + k + i Ns].
+template <int R, int DIR, typename C>
+__device__ __forceinline__ void stockham_pass(C *row, int N, int Ns, int lanes, int lane, const C *tw)
+{
+    constexpr int MAXB = (16 + R - 1) / R;  // N / lanes <= 16 by construction
+    const int nbf = N / R;
+    const int twstep = N / (Ns * R);
+    C v[MAXB][R];
+    int kk[MAXB];
+#pragma unroll
+    for (int m = 0; m < MAXB; ++m) {
+        const int j = lane + m * lanes;
+        if (j < nbf) {
+            const int k = j % Ns;
+            kk[m] = k;
+#pragma unroll
+            for (int i = 0; i < R; ++i) v[m][i] = row[j + i * nbf];
+            if (Ns > 1) {
+#pragma unroll
+                for (int i = 1; i < R; ++i) v[m][i] = twmul<DIR>(v[m][i], tw[i * k * twstep]);
+            }
+            Dft<R, DIR, C>::run(v[m]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MAXB; ++m) {
+        const int j = lane + m * lanes;
+        if (j < nbf) {
+            const int k = kk[m];
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int i = 0; i < R; ++i) row[base + i * Ns] = v[m][i];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename C>
+__device__ __forceinline__ void load_block(C *lds, const C *__restrict__ src, int cnt)
+{
+    if constexpr (sizeof(C) == 8) {
+        // two complex floats per 16-byte access when the block is even-sized
+        if ((cnt & 1) == 0 && (((uintptr_t)src) & 15) == 0) {
+            const float4 *s4 = reinterpret_cast<const float4 *>(src);
+            float4 *l4 = reinterpret_cast<float4 *>(lds);
+            for (int e = threadIdx.x; e < (cnt >> 1); e += kThreads) l4[e] = s4[e];
+            return;
+        }
+    }
+    for (int e = threadIdx.x; e < cnt; e += kThreads) lds[e] = src[e];
+}
+
+template <typename C>
+__device__ __forceinline__ void store_block(C *__restrict__ dst, const C *lds, int cnt,
+                                            typename RealOf<C>::type scale, bool do_scale)
+{
+    if constexpr (sizeof(C) == 8) {
+        if ((cnt & 1) == 0 && (((uintptr_t)dst) & 15) == 0) {
+            float4 *d4 = reinterpret_cast<float4 *>(dst);
+            const float4 *l4 = reinterpret_cast<const float4 *>(lds);
+            for (int e = threadIdx.x; e < (cnt >> 1); e += kThreads) {
+                float4 q = l4[e];
+                if (do_scale) {
+                    q.x *= scale;
+                    q.y *= scale;
+                    q.z *= scale;
+                    q.w *= scale;
+                }
+                d4[e] = q;
+            }
+            return;
+        }
+    }
+    for (int e = threadIdx.x; e < cnt; e += kThreads) {
+        C q = lds[e];
+        if (do_scale) q = cscale(q, scale);
+        dst[e] = q;
+    }
+}
+
+// One work-group's share of a batched row FFT: rows [blk * RW, blk * RW + RW).
+template <typename C, int DIR>
+__device__ __forceinline__ void fft_rows_block(const C *in, C *out, const FftDesc &d, int64_t blk,
+                                               typename RealOf<C>::type scale, bool do_scale, C *lds)
+{
+    const int N = d.N;
+    const int64_t row0 = blk * d.rows_per_wg;
+    const int64_t left = d.nrows - row0;
+    const int rows_here = left < d.rows_per_wg ? (int)left : d.rows_per_wg;
+    const int cnt = rows_here * N;
+    load_block(lds, in + row0 * N, cnt);
+    __syncthreads();
+    const int lanes = d.lanes_per_row;
+    const int row = threadIdx.x / lanes;
+    const int lane = threadIdx.x - row * lanes;
+    C *lrow = lds + row * N;
+    const C *tw = reinterpret_cast<const C *>(d.tw);
+    int Ns = 1;
+    for (int p = 0; p < d.npass; ++p) {
+        switch (d.radix[p]) {
+        case 2: stockham_pass<2, DIR>(lrow, N, Ns, lanes, lane, tw); break;
+        case 3: stockham_pass<3, DIR>(lrow, N, Ns, lanes, lane, tw); break;
+        case 4: stockham_pass<4, DIR>(lrow, N, Ns, lanes, lane, tw); break;
+        case 5: stockham_pass<5, DIR>(lrow, N, Ns, lanes, lane, tw); break;
+        case 8: stockham_pass<8, DIR>(lrow, N, Ns, lanes, lane, tw); break;
+        case 16: stockham_pass<16, DIR>(lrow, N, Ns, lanes, lane, tw); break;
+        default: break;
+        }
+        Ns *= d.radix[p];
+    }
+    store_block(out + row0 * N, lds, cnt, scale, do_scale);
+    __syncthreads();  // the LDS block may be reused by the caller's next unit
+}
+
+}  // namespace fftrw

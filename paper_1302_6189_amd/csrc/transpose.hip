@@ -1,215 +1,18 @@
-// transpose.hip -- the transpose between two decompositions (Fig. 4), fused.
-//
-// The array moves from layout A (decomposition pi_t) to layout B (pi_{t+1}).
-// Consecutive decompositions always have different last axes, so the
-// permutation is a tiled 2-D transpose between u (fastest axis of A) and v
-// (fastest axis of B), batched over the other M-2 axes.  A work-group reads a
-// TU x TV tile (times G batch slices) along u, transposes it through LDS and
-// writes it along v, so both sides are coalesced; with an even u (v) size a
-// thread moves two neighbouring values per 16-byte access.
-//
-// Owner counting: virtual process p owns a contiguous range of rows over the
-// first k axes of its decomposition (Eqs. (13)-(15)).  The first k axes of A
-// never include u and those of B never include v (k < M), so inside a tile
-// A's owner depends only on (slice, v) and B's only on (slice, u).  Each tile
-// computes the two owner vectors once, then counts the (u, v) pairs whose
-// owners differ: the points this tile moves between processes.  Summed over
-// tiles this is the paper's communication amount for the transpose.
+// transpose.hip -- stand-alone launch of the fused transpose (xpose_tile.hpp).
 #include <hip/hip_runtime.h>
 
-#include "cplx.hpp"
-#include "kernels.hpp"
+#include "xpose_tile.hpp"
 
 namespace fftrw {
-
-constexpr int kMaxG = 256;
-
-typedef float xf4 __attribute__((ext_vector_type(4)));
-typedef float xf2 __attribute__((ext_vector_type(2)));
-typedef double xd2 __attribute__((ext_vector_type(2)));
-
-template <typename C> __device__ __forceinline__ C xld(const C *p)
-{
-    if constexpr (sizeof(C) == 8) {
-        xf2 w = __builtin_nontemporal_load(reinterpret_cast<const xf2 *>(p));
-        return mk<C>(w.x, w.y);
-    } else {
-        xd2 w = __builtin_nontemporal_load(reinterpret_cast<const xd2 *>(p));
-        return mk<C>(w.x, w.y);
-    }
-}
-template <typename C> __device__ __forceinline__ void xst(C *p, C v)
-{
-    if constexpr (sizeof(C) == 8) {
-        xf2 w = {v.x, v.y};
-        __builtin_nontemporal_store(w, reinterpret_cast<xf2 *>(p));
-    } else {
-        xd2 w = {v.x, v.y};
-        __builtin_nontemporal_store(w, reinterpret_cast<xd2 *>(p));
-    }
-}
-
-__device__ __forceinline__ int64_t owner_of_row(int64_t r, int64_t P, int64_t R, bool narrow)
-{
-    if (narrow) return (int64_t)(((uint32_t)(r + 1) * (uint32_t)P - 1u) / (uint32_t)R);
-    return ((r + 1) * P - 1) / R;
-}
-
-// coordinates of batch slice s (innermost batch axis first) and its bases
-__device__ __forceinline__ void slice_coords(const XposeDesc &d, int64_t s, int *c, int64_t *ab, int64_t *bb)
-{
-    int64_t a = 0, b = 0;
-    for (int i = 0; i < d.nbat; ++i) {
-        const int64_t q = s / d.bsize[i];
-        const int64_t ci = s - q * d.bsize[i];
-        s = q;
-        c[i] = (int)ci;
-        a += ci * d.ba[i];
-        b += ci * d.bb[i];
-    }
-    *ab = a;
-    *bb = b;
-}
 
 template <typename C, int VU, int VV>
 __global__ void __launch_bounds__(kThreads) xpose_kernel(const C *__restrict__ in, C *__restrict__ out, XposeDesc d)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C *tile = reinterpret_cast<C *>(smem_raw);
-    __shared__ int moved_wg;
-
-    const int TU = d.TU, TV = d.TV;
-    const int ldt = TU + 1;
-    uint32_t t = blockIdx.x;
-    const uint32_t tu = t % (uint32_t)d.tiles_u;
-    t /= (uint32_t)d.tiles_u;
-    const uint32_t tv = t % (uint32_t)d.tiles_v;
-    const uint32_t tg = t / (uint32_t)d.tiles_v;
-    const int64_t u0 = (int64_t)tu * TU, v0 = (int64_t)tv * TV, g0 = (int64_t)tg * d.G;
-    const int nu = (int)min<int64_t>(TU, d.Nu - u0);
-    const int nv = (int)min<int64_t>(TV, d.Nv - v0);
-    const int ng = (int)min<int64_t>(d.G, d.nslices - g0);
-
-    int *own_a = reinterpret_cast<int *>(tile + (size_t)d.G * TV * ldt);
-    int *own_b = own_a + d.G * TV;
-    if (d.count) {
-        if (threadIdx.x == 0) moved_wg = 0;
-        // owner vectors: A's over (slice, v), B's over (slice, u)
-        const bool narrow = d.owner32 != 0;
-        for (int i = threadIdx.x; i < ng * nv; i += kThreads) {
-            const int g = i / nv, iv = i - g * nv;
-            int c[3];
-            int64_t ab, bb;
-            slice_coords(d, g0 + g, c, &ab, &bb);
-            int64_t r = 0;
-            for (int j = 0; j < d.ka; ++j) {
-                const int src = d.srca[j];
-                r += (src == 3 ? v0 + iv : (int64_t)c[src]) * d.wa[j];
-            }
-            int64_t o = owner_of_row(r, d.P, d.Ra, narrow);
-            if (d.mu) o = d.mu[o];
-            own_a[g * TV + iv] = (int)o;
-        }
-        for (int i = threadIdx.x; i < ng * nu; i += kThreads) {
-            const int g = i / nu, iu = i - g * nu;
-            int c[3];
-            int64_t ab, bb;
-            slice_coords(d, g0 + g, c, &ab, &bb);
-            int64_t r = 0;
-            for (int j = 0; j < d.kb; ++j) {
-                const int src = d.srcb[j];
-                r += (src == 4 ? u0 + iu : (int64_t)c[src]) * d.wb[j];
-            }
-            own_b[g * TU + iu] = (int)owner_of_row(r, d.P, d.Rb, narrow);
-        }
-    }
-
-    // load: rows (g, v) of contiguous u-values
-    {
-        const int per_row = TU / VU;
-        const int tx = threadIdx.x % per_row;
-        const int ty = threadIdx.x / per_row;
-        const int ystep = kThreads / per_row;
-        const int nrow = ng * nv;
-        int gcur = -1;
-        int64_t abase = 0;
-        for (int r = ty; r < nrow; r += ystep) {
-            const int g = r / nv;
-            const int iv = r - g * nv;
-            if (g != gcur) {
-                int c[3];
-                int64_t bb;
-                slice_coords(d, g0 + g, c, &abase, &bb);
-                gcur = g;
-            }
-            const int iu = tx * VU;
-            if (iu < nu) {
-                const C *p = in + abase + (v0 + iv) * d.a_sv + u0 + iu;
-                C *trow = tile + (g * TV + iv) * ldt + iu;
-                if constexpr (VU == 2) {
-                    xf4 w = __builtin_nontemporal_load(reinterpret_cast<const xf4 *>(p));
-                    trow[0] = mk<C>(w.x, w.y);
-                    trow[1] = mk<C>(w.z, w.w);
-                } else {
-                    trow[0] = xld(p);
-                }
-            }
-        }
-    }
-    __syncthreads();
-
-    // store: rows (g, u) of contiguous v-values
-    int moved = 0;
-    {
-        const int per_row = TV / VV;
-        const int tx = threadIdx.x % per_row;
-        const int ty = threadIdx.x / per_row;
-        const int ystep = kThreads / per_row;
-        const int nrow = ng * nu;
-        int gcur = -1;
-        int64_t bbase = 0;
-        for (int r = ty; r < nrow; r += ystep) {
-            const int g = r / nu;
-            const int iu = r - g * nu;
-            if (g != gcur) {
-                int c[3];
-                int64_t ab;
-                slice_coords(d, g0 + g, c, &ab, &bbase);
-                gcur = g;
-            }
-            const int iv = tx * VV;
-            if (iv < nv) {
-                C *p = out + bbase + (u0 + iu) * d.b_su + v0 + iv;
-                const C *tcol = tile + (g * TV + iv) * ldt + iu;
-                if constexpr (VV == 2) {
-                    const C a0 = tcol[0], a1 = tcol[ldt];
-                    xf4 w = {a0.x, a0.y, a1.x, a1.y};
-                    __builtin_nontemporal_store(w, reinterpret_cast<xf4 *>(p));
-                } else {
-                    xst(p, tcol[0]);
-                }
-                if (d.count) {
-                    const int ob = own_b[g * TU + iu];
-                    moved += own_a[g * TV + iv] != ob;
-                    if (VV == 2) moved += own_a[g * TV + iv + 1] != ob;
-                }
-            }
-        }
-    }
-    if (d.count) {
-        for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
-        if ((threadIdx.x & 63) == 0 && moved) atomicAdd(&moved_wg, moved);
-        __syncthreads();
-        if (threadIdx.x == 0 && moved_wg) atomicAdd(d.counter, (unsigned long long)moved_wg);
-    }
+    xpose_tile<C, VU, VV>(in, out, d, blockIdx.x, smem_raw);
 }
 
-size_t xpose_lds_bytes(const XposeDesc &d, size_t esz)
-{
-    size_t b = (size_t)d.G * d.TV * (d.TU + 1) * esz;
-    if (d.count) b += (size_t)d.G * (d.TU + d.TV) * sizeof(int);
-    return (b + 15) & ~(size_t)15;
-}
+size_t xpose_lds_bytes(const XposeDesc &d, size_t esz) { return xpose_tile_bytes(d, esz) + 16; }
 
 hipError_t launch_xpose(const XposeDesc &d, size_t esz, const void *in, void *out, hipStream_t s)
 {

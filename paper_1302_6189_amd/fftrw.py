@@ -24,6 +24,7 @@ C64, C128 = 1, 2
 PREC_NATIVE, PREC_SPLIT_F16, PREC_SPLIT_BF16, PREC_SPLIT_BF16X3 = 0, 1, 2, 3
 OWN_LITERAL, OWN_MATCHED = 0, 1
 FLAG_LEAVE_PERMUTED, FLAG_STAGED, FLAG_COUNT_MOVED, FLAG_OWN_MATCHED, FLAG_FUSED_FFT = 1, 2, 4, 8, 16
+FLAG_BATCH_NO_GRAPH = 32
 
 LETTERS = "abcdefgh"
 
@@ -34,6 +35,12 @@ class FftrwError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"fftrw error {code}: {msg}")
         self.code = code
+
+
+class ItemDesc(ctypes.Structure):
+    """fft_item_desc"""
+    _fields_ = [("M", ctypes.c_int), ("dims", ctypes.c_int64 * 5), ("P", ctypes.c_int64),
+                ("order", ctypes.c_int8 * 25), ("has_order", ctypes.c_int)]
 
 
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -66,6 +73,12 @@ _SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_int)]),
     "fft_plan_describe": (ctypes.c_int, [_vp, _i8p, ctypes.c_char_p, ctypes.c_size_t]),
     "fft_destroy": (ctypes.c_int, [_vp]),
+    "fft_batch_plan": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                      ctypes.c_char_p, ctypes.c_uint]),
+    "fft_batch_exec_fwd": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
+    "fft_batch_exec_inv": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
+    "fft_batch_stats": (ctypes.c_int, [_vp, _i64p, _i64p, _i64p, ctypes.POINTER(ctypes.c_int)]),
+    "fft_batch_destroy": (ctypes.c_int, [_vp]),
     "fft_last_error": (ctypes.c_char_p, []),
     "fft_version": (ctypes.c_char_p, []),
 }
@@ -290,6 +303,70 @@ class Plan:
     def destroy(self):
         if getattr(self, "_h", None):
             lib().fft_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Batch:
+    """fft_batch_t: many complex64 transforms in one persistent launch.
+
+    items: sequence of (dims, P) or (dims, P, order); order None = best."""
+
+    def __init__(self, items, flags: int = 0, tune_cache: str | None = None):
+        self.items = []
+        arr = (ItemDesc * len(items))()
+        for i, it in enumerate(items):
+            dims, P = tuple(int(d) for d in it[0]), int(it[1])
+            order = it[2] if len(it) > 2 else None
+            d = arr[i]
+            d.M = len(dims)
+            for a, n in enumerate(dims):
+                d.dims[a] = n
+            d.P = P
+            if order is not None:
+                flat = [a for p in order_from(order, len(dims)) for a in p]
+                for k, a in enumerate(flat):
+                    d.order[k] = a
+                d.has_order = 1
+            self.items.append((dims, P))
+        self.n = len(items)
+        self.flags = int(flags)
+        h = _vp()
+        _check(lib().fft_batch_plan(ctypes.byref(h), self.n, ctypes.cast(arr, ctypes.c_void_p), PREC_NATIVE,
+                                    tune_cache.encode() if tune_cache else None, ctypes.c_uint(self.flags)))
+        self._h = h
+
+    def _ptrs(self, bufs):
+        return (_vp * self.n)(*[_ptr(b) for b in bufs])
+
+    def exec_fwd(self, ins, outs, stream=None):
+        _check(lib().fft_batch_exec_fwd(self._h, self._ptrs(ins), self._ptrs(outs), _stream(stream)))
+
+    def exec_inv(self, ins, outs, stream=None):
+        _check(lib().fft_batch_exec_inv(self._h, self._ptrs(ins), self._ptrs(outs), _stream(stream)))
+
+    def stats(self):
+        """dict: per-item lists of device-counted and analytic amounts, units, error flag."""
+        tot = sum(len(d) for d, _ in self.items)
+        mv, an = (ctypes.c_int64 * tot)(), (ctypes.c_int64 * tot)()
+        units, err = ctypes.c_int64(), ctypes.c_int()
+        _check(lib().fft_batch_stats(self._h, mv, an, ctypes.byref(units), ctypes.byref(err)))
+        out_m, out_a, off = [], [], 0
+        for dims, _ in self.items:
+            M = len(dims)
+            out_m.append(list(mv)[off:off + M])
+            out_a.append(list(an)[off:off + M])
+            off += M
+        return {"moved": out_m, "analytic": out_a, "units": units.value, "error": err.value}
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            lib().fft_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

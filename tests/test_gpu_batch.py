@@ -1,0 +1,96 @@
+"""GPU parity of the batched form: many uneven transforms in one persistent,
+graph-replayed launch, against the FP64 oracle and the per-item path."""
+import numpy as np
+import pytest
+
+from oracle import dft, orders
+from paper_1302_6189_amd import fftrw, inputs
+from tests.gpu_util import empty_dev, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [((12, 15, 16), 5), ((20, 18, 24, 6), 7), ((16, 16, 16), 1), ((27, 25, 12), 64),
+         ((8, 12, 10, 6, 5), 9), ((32, 30, 18), 33), ((45, 6, 50), 2), ((64, 48, 40), 48),
+         ((10, 12, 9, 8), 100), ((6, 5, 8, 4, 3), 30), ((192, 12, 20), 17), ((81, 16, 15), 12)]
+
+
+def _run(batch, xs, fwd=True):
+    ins = [to_dev(x) for x in xs]
+    outs = [empty_dev(x.shape, np.complex64) for x in xs]
+    (batch.exec_fwd if fwd else batch.exec_inv)(ins, outs)
+    return ins, outs
+
+
+def test_small_batch_against_oracle(gpu_lib):
+    xs = [inputs.uniform(d, 50 + i, np.complex64) for i, (d, _) in enumerate(SMALL)]
+    b = fftrw.Batch(SMALL, flags=fftrw.FLAG_COUNT_MOVED)
+    ins, outs = _run(b, xs)
+    st = b.stats()
+    assert st["error"] == 0
+    for i, (dims, P) in enumerate(SMALL):
+        order = fftrw.fft_order_search(dims, P)["best_order"]
+        ref = dft.fftn_direct(xs[i], orders.fft_axis_sequence(order))
+        err = dft.rel_l2(to_host(outs[i]), ref)
+        assert err < 1e-5, (i, dims, P, err)
+        steps, _, ret = fftrw.fft_comm_volume(dims, P, order)
+        assert st["analytic"][i] == steps + [ret]
+        assert st["moved"][i] == st["analytic"][i], (i, st["moved"][i])
+    # inverse round trip through the batch
+    back = [empty_dev(x.shape, np.complex64) for x in xs]
+    b.exec_inv(outs, back)
+    for i, x in enumerate(xs):
+        assert dft.rel_l2(to_host(back[i]), x) < 1e-5
+    assert b.stats()["error"] == 0
+
+
+def test_graph_replays_match_eager(gpu_lib):
+    import torch
+    xs = [inputs.gaussian(d, 70 + i, np.complex64) for i, (d, _) in enumerate(SMALL)]
+    eager = fftrw.Batch(SMALL, flags=fftrw.FLAG_BATCH_NO_GRAPH | fftrw.FLAG_COUNT_MOVED)
+    ins, ref_outs = _run(eager, xs)
+    ref = [to_host(o) for o in ref_outs]
+    ref_moved = eager.stats()["moved"]
+    g = fftrw.Batch(SMALL, flags=fftrw.FLAG_COUNT_MOVED)
+    outs = [empty_dev(x.shape, np.complex64) for x in xs]
+    for rep in range(4):
+        for o in outs:
+            o.zero_()
+        g.exec_fwd(ins, outs)
+        torch.cuda.synchronize()
+        # the program's own eager work between replays
+        junk = torch.randn(1 << 20, device="cuda").sum().item()
+        assert np.isfinite(junk)
+        for i in range(len(xs)):
+            assert np.array_equal(to_host(outs[i]), ref[i]), (rep, i)
+        st = g.stats()
+        assert st["error"] == 0 and st["moved"] == ref_moved
+
+
+def test_batch_matches_per_item_plans(gpu_lib):
+    items = inputs.batch_items(24, seed=5)
+    xs = [inputs.uniform(d, 90 + i, np.complex64) for i, (d, _) in enumerate(items)]
+    b = fftrw.Batch(items, flags=fftrw.FLAG_COUNT_MOVED)
+    ins, outs = _run(b, xs)
+    st = b.stats()
+    assert st["error"] == 0
+    for i, (dims, P) in enumerate(items):
+        p = fftrw.Plan(dims, P, None)
+        y = empty_dev(dims, np.complex64)
+        p.exec_fwd(ins[i], y)
+        assert dft.rel_l2(to_host(outs[i]), to_host(y)) < 2e-6, (i, dims)
+        assert st["moved"][i] == st["analytic"][i]
+
+
+def test_config5_full_batch(gpu_lib):
+    items = inputs.batch_items(256, seed=5)
+    xs = [inputs.uniform(d, 1000 + i, np.complex64) for i, (d, _) in enumerate(items)]
+    b = fftrw.Batch(items, flags=fftrw.FLAG_COUNT_MOVED)
+    ins, outs = _run(b, xs)
+    st = b.stats()
+    assert st["error"] == 0
+    assert all(m == a for m, a in zip(st["moved"], st["analytic"]))
+    for i in (0, 7, 100, 255):
+        dims, P = items[i]
+        order = fftrw.fft_order_search(dims, P)["best_order"]
+        ref = dft.fftn_direct(xs[i], orders.fft_axis_sequence(order))
+        assert dft.rel_l2(to_host(outs[i]), ref) < 1e-5, (i, dims)
