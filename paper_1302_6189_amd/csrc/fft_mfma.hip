@@ -18,6 +18,8 @@
 // in FP64; F16 itself is generated in FP64 on the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "cplx.hpp"
 #include "kernels.hpp"
 
@@ -101,6 +103,17 @@ __device__ __forceinline__ int column_exponent(const float *b, int lane)
     return 15 - e;
 }
 
+__device__ __forceinline__ void wave_sync()
+{
+    // LDS blocks here are private to one wave: order writes before other
+    // lanes' reads with a wave-level barrier (no work-group barrier)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+typedef float mf4v __attribute__((ext_vector_type(4)));
+
 template <int PREC, int DIR>
 __global__ void __launch_bounds__(kThreads)
     fft256_mfma_kernel(const float2 *in, float2 *out, int64_t nrows, const float2 *__restrict__ tw256, float scale,
@@ -108,15 +121,19 @@ __global__ void __launch_bounds__(kThreads)
 {
     using PT = Parts<PREC>;
     using V = typename PT::V;
-    __shared__ float2 ybuf[kThreads / 64][16 * 17];  // one padded 16 x 16 block per wave
+    __shared__ __align__(16) float2 xbuf[kThreads / 64][256];     // row in / row out
+    __shared__ float2 ybuf[kThreads / 64][16 * 17];                // stage-1 result, padded
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;   // lane group 0..3
     const int c = lane & 15;   // column (A: row) index
+    float2 *xb = xbuf[wave];
     float2 *yb = ybuf[wave];
+    const bool im = g >= 2;
+    const int n1base = 8 * (g & 1);
 
-    // A operands [Fr | -Fi] and [Fi | Fr], lane holds row c, k = 8g + v
+    // A operands [Fr | -Fi] and [Fi | Fr], lane holds row c, k = 8g + v (FP64 once per wave)
     V a1[PT::n], a2[PT::n];
     {
         float f1[8], f2[8];
@@ -124,85 +141,95 @@ __global__ void __launch_bounds__(kThreads)
         for (int v = 0; v < 8; ++v) {
             const int k = 8 * g + v;
             const int kk = k & 15;
-            double s, co;
-            sincospi(2.0 * (double)((c * kk) & 15) / 16.0, &s, &co);
-            const float fr = (float)co, fi = (float)(DIR * s);
+            double sn, co;
+            sincospi(2.0 * (double)((c * kk) & 15) / 16.0, &sn, &co);
+            const float fr = (float)co, fi = (float)(DIR * sn);
             f1[v] = k < 16 ? fr : -fi;
             f2[v] = k < 16 ? fi : fr;
         }
         split8<PT>(f1, a1);
         split8<PT>(f2, a2);
     }
-
-    const int64_t row = (int64_t)blockIdx.x * (kThreads / 64) + wave;
-    if (row >= nrows) return;  // whole wave exits together; no block barrier follows
-    const float2 *x = in + row * 256;
-    float2 *y = out + row * 256;
-    const bool im = g >= 2;
-    const int n1base = 8 * (g & 1);
-
-    // ---- stage 1: B[k][c] = x[16 n1 + c], k = 8g + v ----------------------------
-    float b[8];
+    // twiddles w_256^{n2 k1} of this lane (n2 = c, k1 = 4g + v)
+    float2 tw[4];
 #pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        mf2v e = __builtin_nontemporal_load(reinterpret_cast<const mf2v *>(x + 16 * (n1base + v) + c));
-        b[v] = im ? e.y : e.x;
+    for (int v = 0; v < 4; ++v) tw[v] = tw256[c * (4 * g + v)];
+
+    const int64_t wstride = (int64_t)gridDim.x * (kThreads / 64);
+    int64_t row = (int64_t)blockIdx.x * (kThreads / 64) + wave;
+    mf4v p0 = {0.f, 0.f, 0.f, 0.f}, p1 = p0;
+    if (row < nrows) {
+        const mf4v *src = reinterpret_cast<const mf4v *>(in + row * 256);
+        p0 = __builtin_nontemporal_load(src + lane);
+        p1 = __builtin_nontemporal_load(src + 64 + lane);
     }
-    int s1 = column_exponent(b, lane);
-#pragma unroll
-    for (int v = 0; v < 8; ++v) b[v] = ldexpf(b[v], s1);
-    V bp[PT::n];
-    split8<PT>(b, bp);
-    mf4 cr = split_product<PT>(a1, bp);
-    mf4 ci = split_product<PT>(a2, bp);
-
-    // unscale, twiddle w_256^{n2 k1} (k1 = 4g + v, n2 = c) and stage through LDS
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int k1 = 4 * g + v;
-        float2 w = tw256[c * k1];
-        float re = ldexpf(cr[v], -s1), imv = ldexpf(ci[v], -s1);
-        float2 t = DIR < 0 ? cmul(mk<float2>(re, imv), w) : cmulc(mk<float2>(re, imv), w);
-        yb[k1 * 17 + c] = t;
-    }
-    // the LDS block is private to this wave: order its writes before the reads
-    // of other lanes with a wave-level barrier (no work-group barrier, so
-    // waves past the last row may already have exited)
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-    // ---- stage 2: B2[n2][k1] = Y'[k1][n2], column k1 = c ------------------------
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        const float2 e = yb[c * 17 + n1base + v];
-        b[v] = im ? e.y : e.x;
-    }
-    int s2 = column_exponent(b, lane);
-#pragma unroll
-    for (int v = 0; v < 8; ++v) b[v] = ldexpf(b[v], s2);
-    split8<PT>(b, bp);
-    cr = split_product<PT>(a1, bp);
-    ci = split_product<PT>(a2, bp);
-
-    // Z[k2][k1] with k2 = 4g + v, k1 = c lands at y[16 k2 + k1]
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int k2 = 4 * g + v;
-        float re = ldexpf(cr[v], -s2), imv = ldexpf(ci[v], -s2);
-        if (do_scale) {
-            re *= scale;
-            imv *= scale;
+    for (; row < nrows; row += wstride) {
+        reinterpret_cast<mf4v *>(xb)[lane] = p0;
+        reinterpret_cast<mf4v *>(xb)[64 + lane] = p1;
+        const int64_t nxt = row + wstride;
+        if (nxt < nrows) {  // prefetch the next row while this one is transformed
+            const mf4v *src = reinterpret_cast<const mf4v *>(in + nxt * 256);
+            p0 = __builtin_nontemporal_load(src + lane);
+            p1 = __builtin_nontemporal_load(src + 64 + lane);
         }
-        mf2v o = {re, imv};
-        __builtin_nontemporal_store(o, reinterpret_cast<mf2v *>(y + 16 * k2 + c));
+        wave_sync();
+
+        // ---- stage 1: B[k][c] = x[16 n1 + c], k = 8g + v ------------------------
+        float b[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const float2 e = xb[16 * (n1base + v) + c];
+            b[v] = im ? e.y : e.x;
+        }
+        const int s1 = column_exponent(b, lane);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) b[v] = ldexpf(b[v], s1);
+        V bp[PT::n];
+        split8<PT>(b, bp);
+        mf4 cr = split_product<PT>(a1, bp);
+        mf4 ci = split_product<PT>(a2, bp);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float re = ldexpf(cr[v], -s1), imv = ldexpf(ci[v], -s1);
+            yb[(4 * g + v) * 17 + c] = DIR < 0 ? cmul(mk<float2>(re, imv), tw[v]) : cmulc(mk<float2>(re, imv), tw[v]);
+        }
+        wave_sync();
+
+        // ---- stage 2: B2[n2][k1] = Y'[k1][n2], column k1 = c ----------------------
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const float2 e = yb[c * 17 + n1base + v];
+            b[v] = im ? e.y : e.x;
+        }
+        const int s2 = column_exponent(b, lane);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) b[v] = ldexpf(b[v], s2);
+        split8<PT>(b, bp);
+        cr = split_product<PT>(a1, bp);
+        ci = split_product<PT>(a2, bp);
+        // Z[k2][k1] (k2 = 4g + v, k1 = c) lands at y[16 k2 + k1]: stage in xb
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float re = ldexpf(cr[v], -s2), imv = ldexpf(ci[v], -s2);
+            if (do_scale) {
+                re *= scale;
+                imv *= scale;
+            }
+            xb[16 * (4 * g + v) + c] = mk<float2>(re, imv);
+        }
+        wave_sync();
+        mf4v* dst = reinterpret_cast<mf4v *>(out + row * 256);
+        __builtin_nontemporal_store(reinterpret_cast<mf4v *>(xb)[lane], dst + lane);
+        __builtin_nontemporal_store(reinterpret_cast<mf4v *>(xb)[64 + lane], dst + 64 + lane);
+        wave_sync();  // xb is rewritten by the next row
     }
 }
 
 hipError_t launch_fft256_mfma(int precision, int dir, const void *tw256, int64_t nrows, const void *in, void *out,
                               double scale, hipStream_t s)
 {
-    const int64_t nblk = (nrows + 3) / 4;
+    // waves loop over rows; about 8 work-groups per CU of 256
+    const int64_t nblk = std::min<int64_t>((nrows + 3) / 4, 2048);
     if (nblk <= 0) return hipSuccess;
     const int ds = scale != 1.0;
     dim3 grid((unsigned)nblk), block(kThreads);
