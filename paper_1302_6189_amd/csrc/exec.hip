@@ -28,6 +28,9 @@ void pow2_describe(int N, bool fp64, int *tw_count, int *radices, int *npass);
 hipError_t pow2_make_twiddles(int N, bool fp64, void *tw, hipStream_t s);
 hipError_t launch_fft_pow2(int N, bool fp64, const void *tw, int64_t nrows, int dir, const void *in, void *out,
                            double scale, hipStream_t s);
+int pow2_rows_per_wg(int N, bool fp64);
+hipError_t launch_fft_xpose_pow2(int N, bool fp64, const void *tw, const XposeDesc &fx, int dir, const void *in,
+                                 void *out, double scale, hipStream_t s);
 hipError_t launch_fft256_mfma(int precision, int dir, const void *tw256, int64_t nrows, const void *in, void *out,
                               double scale, hipStream_t s);
 hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in, void *out, double scale,
@@ -259,6 +262,28 @@ int run_pipeline(fft_plan_impl *pl, const void *in, void *out, hipStream_t s, in
         return FFTRW_OK;
     };
     if (int rc = mark()) return rc;
+    if (pl->fused && in != out) {
+        // every step is one out-of-place kernel: FFT along u, written in the
+        // next layout; the buffers alternate so the last one lands in out
+        const void *src = in;
+        for (int t = 0; t < nx; ++t) {
+            void *dst = ((nx - 1 - t) % 2 == 0) ? out : pl->work;
+            const double scale = (dir > 0 && t == M - 1) ? 1.0 / (double)pl->T : 1.0;
+            const FftDesc &d = pl->fft[t];
+            HIP_TRY(launch_fft_xpose_pow2(d.N, pl->esz == 16, d.tw, pl->xp[t], dir, src, dst, scale, s),
+                    "fused fft+transpose launch");
+            if (int rc = mark()) return rc;
+            src = dst;
+        }
+        if (leave) {
+            const double scale = dir > 0 ? 1.0 / (double)pl->T : 1.0;
+            if (int rc = run_fft_step(pl, M - 1, dir, out, out, scale, s)) return rc;
+            if (int rc = mark()) return rc;
+        }
+        pl->n_recorded = nev;
+        pl->executed = true;
+        return FFTRW_OK;
+    }
     void *b0 = (nx % 2 == 0) ? out : pl->work;
     void *b1 = (b0 == out) ? pl->work : out;
     void *cur = b0, *other = b1;
@@ -298,7 +323,6 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
     if (flags & ~(unsigned)(FFTRW_FLAG_LEAVE_PERMUTED | FFTRW_FLAG_STAGED | FFTRW_FLAG_COUNT_MOVED |
                             FFTRW_FLAG_OWN_MATCHED | FFTRW_FLAG_FUSED_FFT | FFTRW_FLAG_BATCH_NO_GRAPH))
         return fail(FFTRW_E_ARG, "unknown flag bits");
-    if (flags & FFTRW_FLAG_FUSED_FFT) return fail(FFTRW_E_UNSUPPORTED, "fused FFT+transpose not built yet");
 
     fft_plan_s *pl = new (std::nothrow) fft_plan_s();
     if (!pl) return fail(FFTRW_E_NOMEM, "out of host memory");
@@ -427,6 +451,20 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
                 return rc;
             }
         }
+    }
+    // fusion of every FFT step with its transpose: power-of-two rows short enough
+    // that a work-group's run of consecutive v-values is at least 8 long
+    if ((flags & FFTRW_FLAG_FUSED_FFT) && !(flags & FFTRW_FLAG_STAGED) && precision == FFTRW_PREC_NATIVE &&
+        !generic_rows) {
+        const bool fp64 = pl->esz == 16;
+        const int nx = (flags & FFTRW_FLAG_LEAVE_PERMUTED) ? M - 1 : M;
+        bool ok = true;
+        for (int t = 0; t < M && ok; ++t) {
+            const FftDesc &d = pl->fft[t];
+            ok = d.pow2 && !d.mfma && d.N >= 16 && d.N <= (fp64 ? 256 : 512);
+            if (ok && t < nx) ok = pow2_rows_per_wg(d.N, fp64) <= pl->xp[t].Nv;
+        }
+        pl->fused = ok;
     }
     if (hipDeviceSynchronize() != hipSuccess) {
         free_plan(pl);
@@ -559,7 +597,7 @@ int fft_plan_describe(fft_plan_t plan, int8_t *order, char *text, size_t cap)
     if (!plan) return fail(FFTRW_E_ARG, "null plan");
     if (order) std::memcpy(order, plan->order, (size_t)(plan->M * plan->M));
     if (text && cap) {
-        std::string s;
+        std::string s = plan->fused ? "fused|" : "";
         for (int t = 0; t < plan->M; ++t) {
             if (t) s += ";";
             if (plan->fft[t].mfma) s += "mfma:";

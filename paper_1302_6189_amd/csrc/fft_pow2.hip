@@ -223,6 +223,148 @@ __global__ void __launch_bounds__(kThreads)
     }
 }
 
+// ---- FFT step fused with the transpose that follows it -------------------------
+// A work-group transforms RW rows along u (the last axis of layout A) that are
+// consecutive in v (the last axis of layout B) within one batch slice, then
+// writes the results in layout B: the last pass lands in an LDS staging block
+// S[k][r] and each k becomes one run of RW consecutive v-values in HBM.  Owner
+// counting as in the transpose: A's owner is constant along a row, B's along
+// a run.
+__device__ __forceinline__ int64_t fx_owner(int64_t r, int64_t P, int64_t R, bool narrow)
+{
+    if (narrow) return (int64_t)(((uint32_t)(r + 1) * (uint32_t)P - 1u) / (uint32_t)R);
+    return ((r + 1) * P - 1) / R;
+}
+
+// threads per work-group of the fused kernel: 512 when a 256-thread group
+// would hold fewer than 16 rows (runs of 16 values = 128 bytes)
+template <int N, int E> struct FusedThreads {
+    static constexpr int value = (kThreads / (N / E) < 16 && 512 / (N / E) <= 64) ? 512 : kThreads;
+};
+
+template <typename C, int N, int E, int DIR, class RL>
+__global__ void __launch_bounds__((FusedThreads<N, E>::value))
+    fft_xpose_kernel(const C *in, C *out, XposeDesc d, const C *__restrict__ tw, typename RealOf<C>::type scale,
+                     int do_scale)
+{
+    constexpr int NT = FusedThreads<N, E>::value;
+    constexpr int L = N / E;
+    constexpr int RW = NT / L;
+    constexpr int NP = RL::n;
+    constexpr int SROW = RW + 1;
+    constexpr int LDS_FFT = NP > 1 ? RW * (N + N / 16) : 1;
+    constexpr int LDS_STG = N * SROW;
+    __shared__ C lds[LDS_FFT > LDS_STG ? LDS_FFT : LDS_STG];
+    __shared__ int own_a[RW];
+    __shared__ int own_b[N];
+    __shared__ int moved_wg;
+
+    const int64_t tiles_v = (d.Nv + RW - 1) / RW;
+    const int64_t tv = blockIdx.x % tiles_v;
+    const int64_t slice = blockIdx.x / tiles_v;
+    const int64_t v0 = tv * RW;
+    const int nv = (int)min<int64_t>(RW, d.Nv - v0);
+    int bc[3] = {0, 0, 0};
+    int64_t abase = 0, bbase = 0;
+    {
+        int64_t sl = slice;
+        for (int i = 0; i < d.nbat; ++i) {
+            const int64_t q = sl / d.bsize[i];
+            const int64_t ci = sl - q * d.bsize[i];
+            sl = q;
+            bc[i] = (int)ci;
+            abase += ci * d.ba[i];
+            bbase += ci * d.bb[i];
+        }
+    }
+    if (d.count) {
+        const bool narrow = d.owner32 != 0;
+        if (threadIdx.x == 0) moved_wg = 0;
+        for (int r = threadIdx.x; r < nv; r += NT) {
+            int64_t row = 0;
+            for (int j = 0; j < d.ka; ++j) row += (d.srca[j] == 3 ? v0 + r : (int64_t)bc[d.srca[j]]) * d.wa[j];
+            int64_t o = fx_owner(row, d.P, d.Ra, narrow);
+            if (d.mu) o = d.mu[o];
+            own_a[r] = (int)o;
+        }
+        for (int k = threadIdx.x; k < N; k += NT) {
+            int64_t row = 0;
+            for (int j = 0; j < d.kb; ++j) row += (d.srcb[j] == 4 ? (int64_t)k : (int64_t)bc[d.srcb[j]]) * d.wb[j];
+            own_b[k] = (int)fx_owner(row, d.P, d.Rb, narrow);
+        }
+    }
+
+    const int lane = threadIdx.x % L;
+    const int r = threadIdx.x / L;
+    const bool active = r < nv;
+    const C *src = in + abase + (v0 + r) * d.a_sv;
+    C v[E];
+    {
+        using PI = PassInfo<N, RL, 0>;
+        constexpr int R = PI::R, B = E / R;
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                C t[B];
+                load_run<B>(src + lane * B + i * PI::NB, t);
+#pragma unroll
+                for (int b = 0; b < B; ++b) v[b * R + i] = t[b];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = mk<C>(0, 0);
+        }
+    }
+    run_passes<N, E, DIR, RL, 0>(v, lds + r * (N + N / 16), lane, tw);
+    {   // last pass outputs (row r, k = j + i N/R) into the staging block
+        using PI = PassInfo<N, RL, NP - 1>;
+        constexpr int R = PI::R, B = E / R;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                C q = v[b * R + i];
+                if (do_scale) q = cscale(q, scale);
+                lds[(lane * B + b + i * PI::NB) * SROW + r] = q;
+            }
+    }
+    __syncthreads();
+    // runs of consecutive v for every k, two values per 16-byte store
+    int moved = 0;
+    constexpr int HP = RW / 2;
+    const int npair = (nv + 1) / 2;
+    C *dstb = out + bbase + v0;
+    for (int idx = threadIdx.x; idx < N * HP; idx += NT) {
+        const int rp = idx % HP;
+        const int k = idx / HP;
+        if (rp >= npair) continue;
+        const int r0 = 2 * rp;
+        C *p = dstb + (int64_t)k * d.b_su + r0;
+        const C a0 = lds[k * SROW + r0];
+        if (r0 + 1 < nv) {
+            const C a1 = lds[k * SROW + r0 + 1];
+            if constexpr (sizeof(C) == 8) {
+                using V4 = typename Vec2<float2>::type;
+                V4 w = {a0.x, a0.y, a1.x, a1.y};
+                __builtin_nontemporal_store(w, reinterpret_cast<V4 *>(p));
+            } else {
+                st_nt(p, a0);
+                st_nt(p + 1, a1);
+            }
+            if (d.count) moved += (own_a[r0] != own_b[k]) + (own_a[r0 + 1] != own_b[k]);
+        } else {
+            st_nt(p, a0);
+            if (d.count) moved += own_a[r0] != own_b[k];
+        }
+    }
+    if (d.count) {
+        for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
+        if ((threadIdx.x & 63) == 0 && moved) atomicAdd(&moved_wg, moved);
+        __syncthreads();
+        if (threadIdx.x == 0 && moved_wg) atomicAdd(d.counter, (unsigned long long)moved_wg);
+    }
+}
+
 // radix lists per N (every radix divides E so each thread owns whole butterflies)
 template <int N> struct Pow2Plan;
 template <> struct Pow2Plan<2> { using RL = RadixList<2>; };
@@ -279,7 +421,7 @@ namespace {
 
 template <typename C, int N, int E, class RL>
 hipError_t launch_one(bool make_tw, void *tw, int64_t nrows, int dir, const void *in, void *out, double scale,
-                      hipStream_t s, int *tw_count, int *radices, int *npass)
+                      hipStream_t s, int *tw_count, int *radices, int *npass, const XposeDesc *fx = nullptr)
 {
     if (tw_count) *tw_count = TwSize<N, RL>::value;
     if (npass) {
@@ -297,6 +439,20 @@ hipError_t launch_one(bool make_tw, void *tw, int64_t nrows, int dir, const void
     }
     if (!in) return hipSuccess;
     constexpr int L = N / E, RW = kThreads / L;
+    if (fx) {
+        using Real = typename RealOf<C>::type;
+        constexpr int NTF = FusedThreads<N, E>::value, RWF = NTF / L;
+        const int64_t nblk = ((fx->Nv + RWF - 1) / RWF) * fx->nslices;
+        if (nblk <= 0) return hipSuccess;
+        const int ds = scale != 1.0;
+        if (dir < 0)
+            hipLaunchKernelGGL((fft_xpose_kernel<C, N, E, -1, RL>), dim3((unsigned)nblk), dim3(NTF), 0, s,
+                               (const C *)in, (C *)out, *fx, (const C *)tw, (Real)scale, ds);
+        else
+            hipLaunchKernelGGL((fft_xpose_kernel<C, N, E, 1, RL>), dim3((unsigned)nblk), dim3(NTF), 0, s,
+                               (const C *)in, (C *)out, *fx, (const C *)tw, (Real)scale, ds);
+        return hipGetLastError();
+    }
     const int64_t nblk = (nrows + RW - 1) / RW;
     if (nblk <= 0) return hipSuccess;
     using Real = typename RealOf<C>::type;
@@ -312,16 +468,16 @@ hipError_t launch_one(bool make_tw, void *tw, int64_t nrows, int dir, const void
 
 template <typename C, int N>
 hipError_t dispatch_n(bool make_tw, void *tw, int64_t nrows, int dir, const void *in, void *out, double scale,
-                      hipStream_t s, int *tw_count, int *radices, int *npass)
+                      hipStream_t s, int *tw_count, int *radices, int *npass, const XposeDesc *fx)
 {
     if constexpr (sizeof(C) == 8) {
         constexpr int E = N < 16 ? N : 16;
         return launch_one<C, N, E, typename Pow2Plan<N>::RL>(make_tw, tw, nrows, dir, in, out, scale, s, tw_count,
-                                                             radices, npass);
+                                                             radices, npass, fx);
     } else if constexpr (N <= 2048) {
         constexpr int E = N < 8 ? N : 8;
         return launch_one<C, N, E, typename Pow2Plan64<N>::RL>(make_tw, tw, nrows, dir, in, out, scale, s,
-                                                                tw_count, radices, npass);
+                                                                tw_count, radices, npass, fx);
     } else {
         return hipErrorInvalidValue;
     }
@@ -329,10 +485,11 @@ hipError_t dispatch_n(bool make_tw, void *tw, int64_t nrows, int dir, const void
 
 template <typename C>
 hipError_t dispatch(int N, bool make_tw, void *tw, int64_t nrows, int dir, const void *in, void *out,
-                    double scale, hipStream_t s, int *tw_count, int *radices, int *npass)
+                    double scale, hipStream_t s, int *tw_count, int *radices, int *npass,
+                    const XposeDesc *fx = nullptr)
 {
 #define FFTRW_CASE(n) \
-    case n: return dispatch_n<C, n>(make_tw, tw, nrows, dir, in, out, scale, s, tw_count, radices, npass);
+    case n: return dispatch_n<C, n>(make_tw, tw, nrows, dir, in, out, scale, s, tw_count, radices, npass, fx);
     switch (N) {
         FFTRW_CASE(2) FFTRW_CASE(4) FFTRW_CASE(8) FFTRW_CASE(16) FFTRW_CASE(32) FFTRW_CASE(64)
         FFTRW_CASE(128) FFTRW_CASE(256) FFTRW_CASE(512) FFTRW_CASE(1024) FFTRW_CASE(2048) FFTRW_CASE(4096)
@@ -361,6 +518,22 @@ hipError_t pow2_make_twiddles(int N, bool fp64, void *tw, hipStream_t s)
 {
     return fp64 ? dispatch<double2>(N, true, tw, 0, -1, nullptr, nullptr, 1.0, s, nullptr, nullptr, nullptr)
                 : dispatch<float2>(N, true, tw, 0, -1, nullptr, nullptr, 1.0, s, nullptr, nullptr, nullptr);
+}
+
+// rows per work-group of the fused kernel for N (its run length along v)
+int pow2_rows_per_wg(int N, bool fp64)
+{
+    const int E = fp64 ? (N < 8 ? N : 8) : (N < 16 ? N : 16);
+    const int L = N / E;
+    const int nt = (kThreads / L < 16 && 512 / L <= 64) ? 512 : kThreads;
+    return nt / L;
+}
+
+hipError_t launch_fft_xpose_pow2(int N, bool fp64, const void *tw, const XposeDesc &fx, int dir, const void *in,
+                                 void *out, double scale, hipStream_t s)
+{
+    return fp64 ? dispatch<double2>(N, false, (void *)tw, 0, dir, in, out, scale, s, nullptr, nullptr, nullptr, &fx)
+                : dispatch<float2>(N, false, (void *)tw, 0, dir, in, out, scale, s, nullptr, nullptr, nullptr, &fx);
 }
 
 hipError_t launch_fft_pow2(int N, bool fp64, const void *tw, int64_t nrows, int dir, const void *in, void *out,

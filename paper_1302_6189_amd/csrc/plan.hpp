@@ -53,6 +53,7 @@ struct fft_plan_impl {
     std::map<int, void *> twiddles;
     size_t dev_bytes = 0;
     bool executed = false;
+    bool fused = false;                 // FFT steps fused with the following transpose
 
     // per-stage timing events (fft_plan_set_timing)
     bool timing = false;

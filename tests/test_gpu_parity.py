@@ -213,3 +213,58 @@ def test_default_order_is_best(gpu_lib):
     p = fftrw.Plan(dims, P, None)
     o, _ = p.describe()
     assert o == fftrw.fft_order_search(dims, P)["best_order"]
+
+
+@pytest.mark.parametrize("dims,P,oidx", [((64, 64, 64), 48, 0), ((64, 64, 64), 1000, 3), ((128, 32, 64), 7, 5),
+                                         ((512, 512, 512), 4096, 0), ((16, 32, 64, 128), 300, 777),
+                                         ((32, 16, 64, 32, 16), 100, 123457), ((256, 256, 256), 64, 6)])
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_fused_fft_transpose(gpu_lib, dims, P, oidx, dtype):
+    if dtype == np.complex128 and np.prod(dims) > 1 << 24:
+        pytest.skip("large FP64 case covered by complex64")
+    M = len(dims)
+    order = fftrw.fft_order_at(M, oidx)
+    plan = fftrw.Plan(dims, P, order, dtype=DT[dtype], flags=fftrw.FLAG_FUSED_FFT | fftrw.FLAG_COUNT_MOVED)
+    fused = plan.describe()[1].startswith("fused|")
+    x = inputs.uniform(dims, 11, dtype)
+    xd = to_dev(x)
+    yd = empty_dev(dims, dtype)
+    plan.exec_fwd(xd, yd)
+    analytic, moved = plan.stats()
+    assert moved == analytic
+    if np.prod(dims) <= 1 << 24:
+        ref = dft.fftn_direct(x, orders.fft_axis_sequence(order))
+        assert dft.rel_l2(to_host(yd), ref) < TOL[dtype]
+    else:
+        # full size: against the unfused pipeline (same kernels' arithmetic per row)
+        plain = fftrw.Plan(dims, P, order, dtype=DT[dtype])
+        zd = empty_dev(dims, dtype)
+        plain.exec_fwd(xd, zd)
+        assert np.array_equal(to_host(yd), to_host(zd))
+        del zd
+    zd = empty_dev(dims, dtype)
+    plan.exec_inv(yd, zd)
+    assert dft.rel_l2(to_host(zd), x) < TOL[dtype]
+    # which shapes fuse: rows 16..512 (FP32) / ..256 (FP64) with runs >= 8 along v
+    print("fused" if fused else "unfused", dims, flush=True)
+    if dims in ((64, 64, 64), (512, 512, 512), (256, 256, 256)) and dtype == np.complex64:
+        assert fused
+
+
+def test_fused_leave_permuted_and_in_place(gpu_lib):
+    dims, P = (64, 32, 128, 16), 40
+    order = fftrw.fft_order_at(4, 999)
+    x = inputs.gaussian(dims, 12, np.complex64)
+    ref = dft.fftn_direct(x, orders.fft_axis_sequence(order))
+    plan = fftrw.Plan(dims, P, order, flags=fftrw.FLAG_FUSED_FFT | fftrw.FLAG_LEAVE_PERMUTED | fftrw.FLAG_COUNT_MOVED)
+    xd = to_dev(x)
+    yd = empty_dev(layout_shape(dims, order[-1]), np.complex64)
+    plan.exec_fwd(xd, yd)
+    assert dft.rel_l2(to_host(yd), pipeline.permute_layout(ref, tuple(range(4)), order[-1])) < 1e-5
+    a, m = plan.stats()
+    assert m[:-1] == a[:-1] and m[-1] == -1
+    # in == out falls back to the unfused pipeline and stays correct
+    plan2 = fftrw.Plan(dims, P, order, flags=fftrw.FLAG_FUSED_FFT)
+    xd = to_dev(x)
+    plan2.exec_fwd(xd, xd)
+    assert dft.rel_l2(to_host(xd), ref) < 1e-5
