@@ -207,6 +207,8 @@ def main():
     ap.add_argument("--order", default="best", help="best, worst or a canonical order index")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision and batched legs")
+    ap.add_argument("--staged", action="store_true",
+                    help="also time the staged pack -> exchange -> unpack transposes")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="one forward transform plus a plain 1 GiB device copy, for counter runs")
     args = ap.parse_args()
@@ -353,6 +355,24 @@ def main():
     out["unfused_pipeline"] = {"ms_per_transform": round(ms_plain, 4),
                                "GFLOPs": round(flops_per_transform / (ms_plain * 1e-3) / 1e9, 1),
                                "stage_ms": [round(v, 4) for v in st_plain]}
+    if args.staged:
+        # explicit per-process buffers: pack, exchange of exactly the moved
+        # points, unpack (the exchange's traffic is 2 x 8 x V_t bytes)
+        stg = {}
+        for Ps in sorted({8, P}):
+            t0 = time.perf_counter()
+            sp = fftrw.Plan(dims, Ps, order, dtype=fftrw.C64, flags=fftrw.FLAG_STAGED)
+            plan_s = time.perf_counter() - t0
+            ms_s = time_fwd(sp, x, y, stream, max(3, args.steps // 4), warm=1)
+            sp.set_timing(True)
+            sp.exec_fwd(x, y, stream)
+            st_s = sp.timings()
+            a_s, m_s = sp.stats()
+            stg[f"P{Ps}"] = {"ms_per_transform": round(ms_s, 4), "plan_s": round(plan_s, 2),
+                             "stage_ms": [round(v, 4) for v in st_s], "exchanged_points": m_s,
+                             "analytic": a_s, "device_bytes": sp.workspace_bytes()}
+            sp.destroy()
+        out["staged_pipeline"] = stg
     del x, y, z
     if not args.no_forms:
         torch.cuda.empty_cache()
