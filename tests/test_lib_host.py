@@ -195,3 +195,32 @@ def test_error_codes():
     with pytest.raises(fftrw.FftrwError) as e:
         fftrw.fft_comm_volume((4, 4, 4), 20, "abc->acb->bca")
     assert e.value.code == fftrw.E_ROWSPLIT
+
+
+def test_comparison_with_five_d_method_via_library():
+    # Section 4: on 16^5 the method needs up to ~11.1x less than the 5-D method
+    # (Eq. (25)).  Each distinct transpose amount identity -> rho is read from
+    # fft_comm_volume of an order starting with that transpose (equal sizes:
+    # any transpose reduces to one of these by relabelling the axes).
+    from tests.test_oracle_claims import _claims, _relabel, order_table
+    M, N = 5, 16
+    perms, seq = order_table(M)
+    ident = tuple(range(M))
+    completion = {}
+    for row in seq:
+        o = tuple(perms[i] for i in row)
+        completion.setdefault(o[1], o)
+    best_ratio = 0.0
+    for P in [2 ** k for k in range(1, 17)]:
+        pvd = {}
+        for rho, o in completion.items():
+            steps, _, _ = fftrw.fft_comm_volume((N,) * M, P, o, allow_rowsplit=True)
+            pvd[rho] = steps[0]
+        pv = np.zeros((len(perms), len(perms)), dtype=np.int64)
+        for a in range(len(perms)):
+            for b in range(len(perms)):
+                if perms[a][-1] != perms[b][-1]:
+                    pv[a, b] = pvd[_relabel(perms[a], perms[b])]
+        tot = sum(pv[seq[:, t], seq[:, t + 1]] for t in range(M - 1))
+        best_ratio = max(best_ratio, fftrw.fft_compare_models(N, P)[4] / tot.min())
+    assert round(best_ratio, 1) == _claims()["vs5d_16pow5_max"]
