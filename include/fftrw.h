@@ -304,6 +304,18 @@ int fft_batch_stats(fft_batch_t batch, int64_t *moved, int64_t *analytic,
 
 int fft_batch_destroy(fft_batch_t batch);
 
+/*
+ * fft_autotune -- time candidate kernel parameters for the row lengths and
+ * transposes of the given items on the current device and write the winners
+ * to the JSON file cache_path: per row length, the radix order and rows per
+ * work-group of the generic row kernel; per (u size, v size) transpose, the
+ * tile shape.  The cache records the device architecture and library
+ * version; fft_batch_plan ignores a cache whose tags do not match.  Uses
+ * about 260 MB of device memory while it runs; synchronous.  flags: 0.
+ */
+int fft_autotune(int n, const fft_item_desc *items, const char *cache_path,
+                 unsigned flags);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char *fft_last_error(void);
 

@@ -25,6 +25,7 @@
 #include "fft_generic.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "tune.hpp"
 #include "xpose_tile.hpp"
 
 namespace fftrw {
@@ -144,7 +145,7 @@ __global__ void batch_reset_kernel(unsigned long long *p, int64_t n)
 namespace fftrw {
 
 int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8_t *order, int dtype,
-                int precision, unsigned flags, bool generic_rows);
+                int precision, unsigned flags, bool generic_rows, const TuneTable *tune);
 void plan_free(fft_plan_t plan);
 
 struct fft_batch_impl {
@@ -169,6 +170,7 @@ struct fft_batch_impl {
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     bool pointers_set = false;
+    bool tuned = false;  // a matching autotuner cache was applied
 };
 
 namespace {
@@ -226,8 +228,9 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
                    unsigned flags)
 {
     g_last_error.clear();
-    (void)tune_cache;
     if (!out || !items || n < 1) return fail(FFTRW_E_ARG, "null output, null items or n < 1");
+    TuneTable tune;
+    const bool tuned = tune_cache && tune_load(tune_cache, tune_device_name(), fft_version(), &tune);
     *out = nullptr;
     if (precision != FFTRW_PREC_NATIVE)
         return fail(FFTRW_E_UNSUPPORTED, "the batched form runs the FP32 Stockham kernels");
@@ -246,7 +249,7 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
         const fft_item_desc &it = items[i];
         fft_plan_t p = nullptr;
         int rc = plan_create(&p, it.M, it.dims, it.P, it.has_order ? it.order : nullptr, FFTRW_C64,
-                             FFTRW_PREC_NATIVE, pflags, true);
+                             FFTRW_PREC_NATIVE, pflags, true, tuned ? &tune : nullptr);
         if (rc) {
             std::string m = "item " + std::to_string(i) + ": " + g_last_error;
             batch_free(b);
@@ -346,6 +349,7 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
         batch_free(b);
         return fail(FFTRW_E_NOMEM, "device allocation for the batch failed");
     }
+    b->tuned = tuned;
     *out = b;
     return FFTRW_OK;
 }

@@ -19,6 +19,7 @@
 #include "errors.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "tune.hpp"
 
 namespace fftrw {
 
@@ -105,7 +106,7 @@ i64 pow2ceil(i64 x)
     return p;
 }
 
-int make_fft_desc(fft_plan_impl *pl, int t, FftDesc *d, bool generic_rows)
+int make_fft_desc(fft_plan_impl *pl, int t, FftDesc *d, bool generic_rows, const TuneTable *tune)
 {
     const int ax = pl->order[t * pl->M + pl->M - 1];
     const i64 N = pl->dims[ax];
@@ -132,6 +133,26 @@ int make_fft_desc(fft_plan_impl *pl, int t, FftDesc *d, bool generic_rows)
     const i64 elems = pl->esz == 8 ? 4096 : 2048;
     i64 rw = 1;
     while (rw * 2 <= 256 && rw * 2 * N <= elems) rw *= 2;
+    if (tune) {
+        // autotuned radix order and rows per work-group, checked against the
+        // kernel's limits (radix set, product, LDS size, 16 values per lane)
+        auto it = tune->rows.find((int)N);
+        if (it != tune->rows.end()) {
+            const RowTune &rt = it->second;
+            i64 prod = 1;
+            bool ok = !rt.radix.empty() && (int)rt.radix.size() <= kMaxPasses;
+            for (int r : rt.radix) {
+                ok = ok && (r == 2 || r == 3 || r == 4 || r == 5 || r == 8 || r == 16);
+                prod *= r;
+            }
+            if (ok && prod == N) {
+                d->npass = (int)rt.radix.size();
+                for (int q = 0; q < d->npass; ++q) d->radix[q] = rt.radix[q];
+            }
+            const i64 trw = rt.rows_per_wg;
+            if (trw >= 1 && trw <= rw && (trw & (trw - 1)) == 0) rw = trw;
+        }
+    }
     d->rows_per_wg = (int)rw;
     d->lanes_per_row = (int)(256 / rw);
     d->nrows = pl->T / N;
@@ -139,7 +160,7 @@ int make_fft_desc(fft_plan_impl *pl, int t, FftDesc *d, bool generic_rows)
 }
 
 int make_xpose_desc(fft_plan_impl *pl, const Layout &a, const Layout &b, const std::vector<i64> *mu,
-                    unsigned long long *counter, XposeDesc *d)
+                    unsigned long long *counter, XposeDesc *d, const TuneTable *tune)
 {
     const int M = pl->M;
     std::memset(d, 0, sizeof(*d));
@@ -169,6 +190,18 @@ int make_xpose_desc(fft_plan_impl *pl, const Layout &a, const Layout &b, const s
     d->TV = (int)std::min<i64>(64, pow2ceil(d->Nv));
     const i64 elems = pl->esz == 8 ? 4096 : 2048;
     i64 G = std::max<i64>(1, elems / ((i64)d->TU * d->TV));
+    if (tune) {
+        auto it = tune->tiles.find({(int)d->Nu, (int)d->Nv});
+        if (it != tune->tiles.end()) {
+            const TileTune &tt = it->second;
+            auto pow2ok = [](int x) { return x >= 1 && x <= 64 && (x & (x - 1)) == 0; };
+            if (pow2ok(tt.TU) && pow2ok(tt.TV) && tt.G >= 1 && (i64)tt.G * tt.TU * tt.TV <= elems) {
+                d->TU = tt.TU;
+                d->TV = tt.TV;
+                G = tt.G;
+            }
+        }
+    }
     G = std::min<i64>(G, 256);
     G = std::min<i64>(G, d->nslices);
     d->G = (int)G;
@@ -307,7 +340,7 @@ int run_pipeline(fft_plan_impl *pl, const void *in, void *out, hipStream_t s, in
 // Build a plan; generic_rows forces the runtime-radix row kernel for every
 // step (the persistent batched kernel runs only that one).
 int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8_t *order, int dtype,
-                int precision, unsigned flags, bool generic_rows)
+                int precision, unsigned flags, bool generic_rows, const TuneTable *tune)
 {
     g_last_error.clear();
     if (!plan) return fail(FFTRW_E_ARG, "plan must not be null");
@@ -386,7 +419,7 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
     // FFT descriptors and twiddles
     pl->fft.resize(M);
     for (int t = 0; t < M; ++t) {
-        rc = make_fft_desc(pl, t, &pl->fft[t], generic_rows);
+        rc = make_fft_desc(pl, t, &pl->fft[t], generic_rows, tune);
         if (rc) {
             free_plan(pl);
             return rc;
@@ -438,7 +471,7 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
     pl->staged.resize(M);
     for (int t = 0; t < M; ++t) {
         unsigned long long *ctr = (flags & FFTRW_FLAG_COUNT_MOVED) ? pl->counters + t : nullptr;
-        rc = make_xpose_desc(pl, pl->lay[t], pl->lay[t + 1], &pl->mu[t], ctr, &pl->xp[t]);
+        rc = make_xpose_desc(pl, pl->lay[t], pl->lay[t + 1], &pl->mu[t], ctr, &pl->xp[t], tune);
         if (rc) {
             free_plan(pl);
             return rc;
@@ -485,7 +518,7 @@ extern "C" {
 int fft_plan(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8_t *order, int dtype,
              int precision, unsigned flags)
 {
-    return fftrw::plan_create(plan, M, dims, P, order, dtype, precision, flags, false);
+    return fftrw::plan_create(plan, M, dims, P, order, dtype, precision, flags, false, nullptr);
 }
 
 int fft_exec_fwd(fft_plan_t plan, const void *in, void *out, void *stream)

@@ -79,6 +79,7 @@ _SIGNATURES = {
     "fft_batch_exec_inv": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
     "fft_batch_stats": (ctypes.c_int, [_vp, _i64p, _i64p, _i64p, ctypes.POINTER(ctypes.c_int)]),
     "fft_batch_destroy": (ctypes.c_int, [_vp]),
+    "fft_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_uint]),
     "fft_last_error": (ctypes.c_char_p, []),
     "fft_version": (ctypes.c_char_p, []),
 }
@@ -312,28 +313,39 @@ class Plan:
             pass
 
 
+def _item_array(items):
+    arr = (ItemDesc * len(items))()
+    for i, it in enumerate(items):
+        dims, P = tuple(int(d) for d in it[0]), int(it[1])
+        order = it[2] if len(it) > 2 else None
+        d = arr[i]
+        d.M = len(dims)
+        for a, n in enumerate(dims):
+            d.dims[a] = n
+        d.P = P
+        if order is not None:
+            flat = [a for p in order_from(order, len(dims)) for a in p]
+            for k, a in enumerate(flat):
+                d.order[k] = a
+            d.has_order = 1
+    return arr
+
+
+def fft_autotune(items, cache_path: str):
+    """Time kernel parameters for the items' row lengths and transposes on the
+    current device and write the winners to cache_path (JSON)."""
+    arr = _item_array(items)
+    _check(lib().fft_autotune(len(items), ctypes.cast(arr, ctypes.c_void_p), cache_path.encode(), 0))
+
+
 class Batch:
     """fft_batch_t: many complex64 transforms in one persistent launch.
 
     items: sequence of (dims, P) or (dims, P, order); order None = best."""
 
     def __init__(self, items, flags: int = 0, tune_cache: str | None = None):
-        self.items = []
-        arr = (ItemDesc * len(items))()
-        for i, it in enumerate(items):
-            dims, P = tuple(int(d) for d in it[0]), int(it[1])
-            order = it[2] if len(it) > 2 else None
-            d = arr[i]
-            d.M = len(dims)
-            for a, n in enumerate(dims):
-                d.dims[a] = n
-            d.P = P
-            if order is not None:
-                flat = [a for p in order_from(order, len(dims)) for a in p]
-                for k, a in enumerate(flat):
-                    d.order[k] = a
-                d.has_order = 1
-            self.items.append((dims, P))
+        arr = _item_array(items)
+        self.items = [(tuple(int(d) for d in it[0]), int(it[1])) for it in items]
         self.n = len(items)
         self.flags = int(flags)
         h = _vp()

@@ -94,3 +94,37 @@ def test_config5_full_batch(gpu_lib):
         order = fftrw.fft_order_search(dims, P)["best_order"]
         ref = dft.fftn_direct(xs[i], orders.fft_axis_sequence(order))
         assert dft.rel_l2(to_host(outs[i]), ref) < 1e-5, (i, dims)
+
+
+def test_autotuned_batch(gpu_lib, tmp_path):
+    import json
+    items = inputs.batch_items(32, seed=5)
+    cache = str(tmp_path / "tune.json")
+    fftrw.fft_autotune(items, cache)
+    with open(cache) as f:
+        rec = json.load(f)
+    assert rec["device"].startswith("gfx950") and rec["version"].startswith("fftrw")
+    lengths = {d[a] for d, _ in items for a in range(len(d))}
+    assert {r["n"] for r in rec["rows"]} == lengths
+    for r in rec["rows"]:
+        assert np.prod(r["radix"]) == r["n"]
+    xs = [inputs.uniform(d, 300 + i, np.complex64) for i, (d, _) in enumerate(items)]
+    b = fftrw.Batch(items, flags=fftrw.FLAG_COUNT_MOVED, tune_cache=cache)
+    ins, outs = _run(b, xs)
+    st = b.stats()
+    assert st["error"] == 0 and st["moved"] == st["analytic"]
+    for i in (0, 5, 17, 31):
+        dims, P = items[i]
+        order = fftrw.fft_order_search(dims, P)["best_order"]
+        ref = dft.fftn_direct(xs[i], orders.fft_axis_sequence(order))
+        assert dft.rel_l2(to_host(outs[i]), ref) < 1e-5
+    # a cache for another device is ignored (same results as no cache)
+    rec["device"] = "other"
+    with open(cache, "w") as f:
+        json.dump(rec, f)
+    b2 = fftrw.Batch(items, tune_cache=cache)
+    ins2, outs2 = _run(b2, xs)
+    plain = fftrw.Batch(items)
+    ins3, outs3 = _run(plain, xs)
+    for i in range(len(items)):
+        assert np.array_equal(to_host(outs2[i]), to_host(outs3[i]))
