@@ -59,6 +59,9 @@ struct BatchCounters {
     unsigned long long next[kMaxStages];
 };
 
+// task starts of one level held in LDS for the per-unit search
+constexpr int kLevelTasksLds = 1024;
+
 // real-time clock ticks (100 MHz) a work-group may wait at one barrier
 constexpr unsigned long long kWaitTicks = 200000000ull;
 
@@ -74,24 +77,26 @@ __global__ void __launch_bounds__(kThreads)
                  BatchCounters *ctr)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int64_t s_unit;
+    __shared__ int64_t s_unit0[kLevelTasksLds];
     for (int lv = 0; lv < nlevels; ++lv) {
         const int64_t nunits = level_units[lv];
         const int t0 = level_task0[lv], t1 = level_task0[lv + 1];
-        for (;;) {
-            if (threadIdx.x == 0) s_unit = (int64_t)atomicAdd(&ctr->next[lv], 1ull);
-            __syncthreads();
-            const int64_t u = s_unit;
-            __syncthreads();  // every thread has read s_unit before it changes
-            if (u >= nunits) break;
-            int lo = t0, hi = t1 - 1;
+        // the level's task starts, searched in LDS when they fit
+        const bool in_lds = t1 - t0 <= kLevelTasksLds;
+        if (in_lds)
+            for (int i = threadIdx.x; i < t1 - t0; i += kThreads) s_unit0[i] = tasks[t0 + i].unit0;
+        __syncthreads();
+        // units are dealt out round-robin: no shared claim counter
+        for (int64_t u = blockIdx.x; u < nunits; u += gridDim.x) {
+            int lo = 0, hi = t1 - t0 - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (tasks[mid].unit0 <= u)
+                if ((in_lds ? s_unit0[mid] : tasks[t0 + mid].unit0) <= u)
                     lo = mid;
                 else
                     hi = mid - 1;
             }
+            lo += t0;
             const BatchTask tk = tasks[lo];
             const BatchItemDev &it = items[tk.item];
             const int64_t local = u - tk.unit0;
@@ -311,7 +316,7 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
     b->nctr = (int64_t)(sizeof(BatchCounters) / sizeof(unsigned long long));
     for (int i = 0; i < n; ++i) {
         b->moved_off[i] = b->nctr;
-        b->nctr += b->h_items[i].M;
+        b->nctr += (int64_t)b->h_items[i].M * kCountBlock;
     }
     int dev = 0, ncu = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -331,7 +336,8 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
         // block, which the graph's reset kernel clears before each launch
         for (int i = 0; i < n; ++i)
             for (int t = 0; t < b->h_items[i].M; ++t)
-                if (b->h_items[i].xp[t].count) b->h_items[i].xp[t].counter = b->d_ctr + b->moved_off[i] + t;
+                if (b->h_items[i].xp[t].count)
+                    b->h_items[i].xp[t].counter = b->d_ctr + b->moved_off[i] + (int64_t)t * kCountBlock;
     }
     if (e == hipSuccess)
         e = hipMemcpy(b->d_tasks, b->h_tasks.data(), sizeof(BatchTask) * b->h_tasks.size(), hipMemcpyHostToDevice);
@@ -421,8 +427,15 @@ int fft_batch_stats(fft_batch_t b, int64_t *moved, int64_t *analytic, int64_t *u
         const int M = b->h_items[i].M;
         for (int t = 0; t < M; ++t) {
             if (analytic) analytic[off + t] = b->plans[i]->analytic[t];
-            if (moved)
-                moved[off + t] = (counted && !(leave && t == M - 1)) ? (int64_t)h[b->moved_off[i] + t] : -1;
+            if (moved) {
+                int64_t sum = -1;
+                if (counted && !(leave && t == M - 1)) {
+                    sum = 0;
+                    for (int k = 0; k < kCountSlots; ++k)
+                        sum += (int64_t)h[b->moved_off[i] + (int64_t)t * kCountBlock + (int64_t)k * kCountStride];
+                }
+                moved[off + t] = sum;
+            }
         }
         off += M;
     }

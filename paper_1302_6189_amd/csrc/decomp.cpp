@@ -262,12 +262,20 @@ std::vector<PairCount> pair_counts(const Layout &a, const Layout &b)
 {
     std::vector<PairCount> out;
     std::vector<std::pair<i64, i64>> acc;
+    // every destination's boxes, computed once
+    std::vector<Box> qbox;
+    std::vector<i64> qfirst(b.P + 1, 0);
+    for (i64 q = 0; q < b.P; ++q) {
+        qfirst[q] = (i64)qbox.size();
+        for (const Box &C : range_boxes(b, q)) qbox.push_back(C);
+    }
+    qfirst[b.P] = (i64)qbox.size();
     for (i64 p = 0; p < a.P; ++p) {
         acc.clear();
         for (const Box &B : range_boxes(a, p)) {
             for_each_owner(b, B, [&](i64 q) {
                 i64 n = 0;
-                for (const Box &C : range_boxes(b, q)) n += box_overlap(B, C, a.M);
+                for (i64 j = qfirst[q]; j < qfirst[q + 1]; ++j) n += box_overlap(B, qbox[j], a.M);
                 if (n) acc.emplace_back(q, n);
             });
         }

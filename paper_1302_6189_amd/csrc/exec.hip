@@ -287,7 +287,7 @@ int run_pipeline(fft_plan_impl *pl, const void *in, void *out, hipStream_t s, in
     const int M = pl->M;
     const bool leave = (pl->flags & FFTRW_FLAG_LEAVE_PERMUTED) != 0;
     const int nx = leave ? M - 1 : M;
-    if (pl->counters) HIP_TRY(launch_zero_u64(pl->counters, M, s), "counter reset");
+    if (pl->counters) HIP_TRY(launch_zero_u64(pl->counters, M * kCountBlock, s), "counter reset");
     int nev = 0;
     auto mark = [&]() -> int {
         if (!pl->timing) return FFTRW_OK;
@@ -445,7 +445,7 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
     // workspace and counters
     rc = dev_alloc(pl, &pl->work, (size_t)pl->T * pl->esz);
     if (!rc && (flags & (FFTRW_FLAG_COUNT_MOVED | FFTRW_FLAG_STAGED)))
-        rc = dev_alloc(pl, (void **)&pl->counters, sizeof(unsigned long long) * (size_t)M);
+        rc = dev_alloc(pl, (void **)&pl->counters, sizeof(unsigned long long) * (size_t)M * kCountBlock);
     if (rc) {
         free_plan(pl);
         return rc;
@@ -470,7 +470,8 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
     pl->xp.resize(M);
     pl->staged.resize(M);
     for (int t = 0; t < M; ++t) {
-        unsigned long long *ctr = (flags & FFTRW_FLAG_COUNT_MOVED) ? pl->counters + t : nullptr;
+        unsigned long long *ctr =
+            (flags & FFTRW_FLAG_COUNT_MOVED) ? pl->counters + (size_t)t * kCountBlock : nullptr;
         rc = make_xpose_desc(pl, pl->lay[t], pl->lay[t + 1], &pl->mu[t], ctr, &pl->xp[t], tune);
         if (rc) {
             free_plan(pl);
@@ -552,7 +553,7 @@ int fft_exec_transpose(fft_plan_t plan, int t, const void *in, void *out, void *
     if (in == out) return fail(FFTRW_E_ARG, "a transpose cannot run in place");
     hipStream_t s = (hipStream_t)stream;
     if (plan->counters) {
-        hipError_t e = launch_zero_u64(plan->counters + t, 1, s);
+        hipError_t e = launch_zero_u64(plan->counters + (size_t)t * kCountBlock, kCountBlock, s);
         if (e != hipSuccess) return fail(FFTRW_E_DEVICE, hipGetErrorString(e));
     }
     int rc = run_transpose(plan, t, in, out, s);
@@ -570,15 +571,19 @@ int fft_plan_stats(fft_plan_t plan, int64_t *per_step, int64_t *moved)
     if (moved) {
         for (int t = 0; t < M; ++t) moved[t] = -1;
         if (plan->counters && plan->executed) {
-            std::vector<unsigned long long> h(M);
+            std::vector<unsigned long long> h((size_t)M * kCountBlock);
             if (hipDeviceSynchronize() != hipSuccess)
                 return fail(FFTRW_E_DEVICE, "device error before reading counters");
-            if (hipMemcpy(h.data(), plan->counters, sizeof(unsigned long long) * M, hipMemcpyDeviceToHost) !=
+            if (hipMemcpy(h.data(), plan->counters, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost) !=
                 hipSuccess)
                 return fail(FFTRW_E_DEVICE, "reading counters failed");
             const bool leave = (plan->flags & FFTRW_FLAG_LEAVE_PERMUTED) != 0;
-            for (int t = 0; t < M; ++t)
-                if (!(leave && t == M - 1)) moved[t] = (int64_t)h[t];
+            for (int t = 0; t < M; ++t) {
+                if (leave && t == M - 1) continue;
+                unsigned long long sum = 0;
+                for (int k = 0; k < kCountSlots; ++k) sum += h[(size_t)t * kCountBlock + (size_t)k * kCountStride];
+                moved[t] = (int64_t)sum;
+            }
         }
     }
     return FFTRW_OK;

@@ -361,7 +361,8 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
         for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
         if ((threadIdx.x & 63) == 0 && moved) atomicAdd(&moved_wg, moved);
         __syncthreads();
-        if (threadIdx.x == 0 && moved_wg) atomicAdd(d.counter, (unsigned long long)moved_wg);
+        if (threadIdx.x == 0 && moved_wg)
+            atomicAdd(d.counter + (blockIdx.x % kCountSlots) * kCountStride, (unsigned long long)moved_wg);
     }
 }
 

@@ -8,6 +8,14 @@ namespace fftrw {
 constexpr int kMaxPasses = 12;
 constexpr int kThreads = 256;  // work-group size of every kernel here (4 waves of 64)
 
+// A device owner-change counter is kCountSlots partial sums on separate
+// 128-byte lines; work-group i adds to slot i % kCountSlots and readers sum
+// the slots.  One address shared by every work-group would serialise their
+// atomics across the chip's L2 slices.
+constexpr int kCountSlots = 32;
+constexpr int kCountStride = 16;  // 64-bit words between slots
+constexpr int kCountBlock = kCountSlots * kCountStride;
+
 // One batched 1-D FFT pass set: nrows contiguous rows of length N, transformed
 // by Stockham autosort passes with the given radices (product = N).
 struct FftDesc {
@@ -46,7 +54,7 @@ struct XposeDesc {
     int64_t Ra, Rb, P;
     int owner32;             // (r+1) P - 1 fits in 32 bits for both layouts
     const int *mu;           // relabelling of A's ranges (nullable = identity)
-    unsigned long long *counter;
+    unsigned long long *counter;  // kCountBlock words (slots, see kCountSlots)
 };
 
 }  // namespace fftrw

@@ -12,17 +12,27 @@
 
 namespace fftrw {
 
+// Tiling of a staged pack or unpack kernel (see staged.hip).
+struct StagedTileCfg {
+    XposeDesc d;                  // geometry; batch axis 0 is the tile's slice axis
+    int lu = 0, lv = 0, lg = 0;   // log2 of the tile's extents along u, v, slices
+    int lane_r = 0, lane_w = 0;   // axis fastest across lanes when reading / writing
+    int srcpos[kMaxDims] = {};    // per A position: batch index 0..2, 3 = v, 4 = u
+    int vpos = 0;                 // A position of v
+};
+
 // Staged transpose tables (pack -> exchange -> unpack), see staged.hip.
 struct StagedStep {
-    int64_t nbox = 0;
-    void *boxes = nullptr;        // device BoxCopy[nbox]
-    void *pack_prefix = nullptr;  // device int64[nbox+1] tile prefix for pack
-    void *unpack_prefix = nullptr;
-    int64_t pack_tiles = 0, unpack_tiles = 0;
+    int64_t npair = 0;            // (p, q) pairs that share points
+    void *recv_info = nullptr;    // device RecvInfo[P]: destination ranges
+    void *send_info = nullptr;    // device SendInfo[P]: source ranges
+    int nbp = 0, nbq = 0;         // boxes per source / destination range
     int64_t nseg = 0;
     void *segs = nullptr;         // device SegCopy[nseg] (p != q only)
-    void *seg_prefix = nullptr;   // device int64[nseg+1] element prefix
+    void *chunk_seg = nullptr;    // device int64[2 * chunks]: first/last segment of each exchange chunk
     int64_t seg_elems = 0;        // = the transpose's amount (points exchanged)
+    int seg_axis = -1;            // natural axis along which segments run
+    StagedTileCfg pack, unpack;   // tilings of the two kernels
 };
 
 struct fft_plan_impl {

@@ -3,22 +3,47 @@
 // This is the all-to-all the paper's processes perform, with every virtual
 // process's buffers held explicitly on the device:
 //   pack:     process p copies the points of its range in decomposition A into
-//             its send buffer, one segment per destination q (ascending q);
-//   exchange: every segment with q != p is copied into q's receive buffer
-//             (segments ordered by source p) -- exactly the points that change
+//             its send region (the same positions as its range), one segment
+//             per destination q in ascending q;
+//   exchange: every segment with q != p is copied into q's receive region
+//             (segments in ascending p) -- exactly the points that change
 //             owner, i.e. the paper's communication amount, counted on the
 //             device;
 //   unpack:   process q places its received segments, and the segment it kept
-//             for itself (read straight from its send buffer), into its range
+//             for itself (read straight from the send array), into its range
 //             of decomposition B.
-// A (p, q) segment is the intersection of p's range in A with q's range in B:
-// a union of axis-aligned boxes (each range is at most 2k-1 boxes).  Inside a
-// segment the boxes follow p's range order and the points of a box run in A's
-// axis order; sender and receiver both derive that convention from the plan,
-// so nothing but point values is exchanged.
+// Inside a segment the points keep A's order, so a segment is a contiguous
+// message and sender and receiver agree on it without exchanging indices.
+//
+// Positions come from closed forms rather than per-point searches.  Let S_p
+// be p's range in A, Q_q be q's range in B (each at most 2k-1 boxes) and
+// rank_q(z) the number of points of Q_q that precede z in A's order (a box
+// count, O(M) per box).  For a point z owned by p in A and by q in B:
+//   send position    = D(p, q) + rank_q(z)
+//   receive position = start_q + rank_q(z) - (p > q ? kept_q : 0)      (p != q)
+//   kept position    = D(q, q) + rank_q(z)                              (p == q)
+// with D(p, q) = xs_p + segoff(p, q) - rank_q(first point of p), where
+// segoff(p, q), the points of S_p in segments for destinations below q, is the
+// number of points of S_p that precede q's first point in B's order -- again
+// a box count.  rank_q grows by one along u (A's fastest axis) inside a run of
+// constant q, and for a fixed (slice, u) it is affine in v (B's fastest axis):
+// v never selects B's owner, so stepping v skips exactly the points of Q_q
+// that share the slice.
+//
+// Both pack and unpack are LDS-tiled over a 3-D block of (u, v, slices along
+// one batch axis).  Reads and writes each run along whichever of the three
+// axes is contiguous on their side: A is contiguous along u, B along v, and a
+// segment along the innermost axis (in A's order) that a typical (p, q) box
+// spans -- u when q owns long runs of u, otherwise v or a batch axis (for
+// example one value of u and of v but 64 slices per segment).  The plan picks
+// that axis and the tile's extents per transpose.  A tile first computes its
+// owners, then its ranks and pair constants as one independent task per
+// (entry, box), summed with LDS atomics, so the few global loads they need
+// are all in flight together.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -27,16 +52,35 @@
 #include "errors.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "xpose_tile.hpp"
 
 namespace fftrw {
 
-struct BoxCopy {
+constexpr int kRangeBoxes = 2 * (kMaxDims - 1) - 1;  // ranges split at most M - 1 axes
+
+// One box of a range in some axis order, with the number of box points per
+// unit step of each axis in that order.  Unused boxes have lo = INT_MAX and
+// count nothing.
+struct RankBox {
     int lo[kMaxDims];
-    int ext[kMaxDims];
-    int64_t send_off;  // first point in the global send array
-    int64_t recv_off;  // first point in the global receive array
-    int self;          // p == q: unpack reads the send array
+    int hi[kMaxDims];
+    int64_t suf[kMaxDims];
+};
+
+struct RecvInfo {              // destination q: its range in B
+    int64_t start;             // first point of the range = start of q's receive region
+    int64_t kept;              // points q owns in both A and B (never exchanged)
+    int64_t selfbase;          // D(q, q)
+    int first_b[kMaxDims];     // q's first point, coordinates in B's order
     int pad;
+    RankBox box[kRangeBoxes];  // in A's order
+};
+
+struct SendInfo {              // source p: its range in A
+    int64_t xs;                // first point of the range = start of p's send region
+    int first_a[kMaxDims];     // p's first point, coordinates in A's order
+    int pad;
+    RankBox box[kRangeBoxes];  // in B's order
 };
 
 struct SegCopy {
@@ -45,19 +89,338 @@ struct SegCopy {
     int64_t len;
 };
 
-struct StagedArgs {
+// Tiling of the pack and unpack kernels.  A tile spans TU values of u, TV of
+// v and G consecutive slices along the first batch axis of d.  Elements are
+// visited with one axis fastest across lanes when read (lane_r) and another
+// when written (lane_w): 0 = u, 1 = v, 2 = slices.
+struct StagedTile {
+    XposeDesc d;
+    int lu, lv, lg;         // log2 of TU, TV, G
+    int lane_r, lane_w;
     int M;
-    int ord_a[kMaxDims];     // natural axes of A from slowest to fastest
-    int64_t stride_a[kMaxDims], stride_b[kMaxDims];
-    const BoxCopy *boxes;    // sorted by send_off (pack) or by recv_off (unpack)
-    int64_t nbox;
-    int64_t total;           // points covered (T, or the exchanged count)
+    int nbp, nbq;           // boxes per range in A and in B
+    int srcpos[kMaxDims];   // per A position: batch index 0..2, 3 = v, 4 = u
+    int vpos;               // A position of v
+    int64_t T;
+    const RecvInfo *recv;
+    const SendInfo *send;
+};
+
+struct ExchangeArgs {
     const SegCopy *segs;
-    int64_t nseg;
+    const int64_t *chunk_seg;  // per chunk: first and last segment it touches
+    int64_t nseg, total;
     unsigned long long *counter;
 };
 
-constexpr int kChunk = 4096;  // points per work-group
+// points of box B that precede coordinates c in the box's axis order
+__device__ __forceinline__ int64_t box_rank(const RankBox &B, const int *c, int M)
+{
+    int64_t r = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxDims; ++i) {
+        if (i >= M) break;
+        const int x = c[i];
+        if (x < B.lo[i]) break;
+        if (x > B.hi[i]) {
+            r += (int64_t)(B.hi[i] - B.lo[i] + 1) * B.suf[i];
+            break;
+        }
+        r += (int64_t)(x - B.lo[i]) * B.suf[i];
+    }
+    return r;
+}
+
+// D(p, q), summed box by box (the slow path of tiles with many pairs, in a
+// loop of its own so the common loop stays small)
+__device__ __forceinline__ int64_t pair_base(const StagedTile &a, int p, int q)
+{
+    const SendInfo &S = a.send[p];
+    const RecvInfo &R = a.recv[q];
+    int64_t r = S.xs;
+    for (int j = 0; j < a.nbp; ++j) {
+        const RankBox B = S.box[j];
+        r += box_rank(B, R.first_b, a.M);
+    }
+    for (int j = 0; j < a.nbq; ++j) {
+        const RankBox B = R.box[j];
+        r -= box_rank(B, S.first_a, a.M);
+    }
+    return r;
+}
+
+constexpr int kPairTab = 1024;  // dense (p, q) constants per pack tile
+constexpr int kTileItems = 16;  // tile elements per thread (tiles hold at most 4096)
+
+struct TileLds {
+    size_t tile, gbase, r0, wv, rb, sb, kp, pt, own_a, own_b, misc, total;
+};
+
+__host__ __device__ inline TileLds tile_lds(int lu, int lv, int lg, size_t esz, bool pack)
+{
+    const size_t TU = (size_t)1 << lu, TV = (size_t)1 << lv, G = (size_t)1 << lg;
+    const size_t SG = TV * (TU + 1) + 1;
+    TileLds L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = (o + bytes + 15) & ~(size_t)15;
+        return at;
+    };
+    L.tile = take(G * SG * esz);
+    L.gbase = take(G * 4);
+    L.r0 = take(G * TU * 4);
+    L.wv = take(G * TU * 4);
+    L.rb = pack ? 0 : take(G * TU * 4);
+    L.sb = pack ? 0 : take(G * TU * 4);
+    L.kp = pack ? 0 : take(G * TU * 4);
+    L.pt = pack ? take(kPairTab * 4) : 0;
+    L.own_a = take(G * TV * 4);
+    L.own_b = take(G * TU * 4);
+    L.misc = take(16);
+    L.total = o;
+    return L;
+}
+
+__device__ __forceinline__ void lds_add(int *p, int64_t v)
+{
+    if (v) atomicAdd(p, (int)v);
+}
+
+// One pass over a tile with axis LANE fastest across lanes: thread t owns lane
+// position t mod E (E = the axis's extent) and lines t / E, t / E + 256 / E, ...
+// of the other two axes.  f(j, g, iv, iu) is called for every element inside
+// the tile's valid extents, j numbering the thread's items.
+template <int LANE, class F>
+__device__ __forceinline__ void tile_pass(int lu, int lv, int lg, int nu, int nv, int ng, F &&f)
+{
+    const int le = LANE == 0 ? lu : (LANE == 1 ? lv : lg);
+    const int x = threadIdx.x & ((1 << le) - 1);
+    const int r0 = threadIdx.x >> le;
+    const int rstep = kThreads >> le;
+    const int nlines = 1 << (lu + lv + lg - le);
+#pragma unroll
+    for (int j = 0; j < kTileItems; ++j) {
+        const int r = r0 + j * rstep;
+        if (r >= nlines) break;
+        int g, iv, iu;
+        if (LANE == 0) {
+            iu = x;
+            iv = r & ((1 << lv) - 1);
+            g = r >> lv;
+        } else if (LANE == 1) {
+            iv = x;
+            iu = r & ((1 << lu) - 1);
+            g = r >> lu;
+        } else {
+            g = x;
+            iu = r & ((1 << lu) - 1);
+            iv = r >> lu;
+        }
+        if (g < ng && iv < nv && iu < nu) f(j, g, iv, iu);
+    }
+}
+
+// PACK:   src = layout A, dst = send array.
+// UNPACK: src = receive array, self_src = send array (kept segments), dst = layout B.
+template <typename C, bool PACK, int LR, int LW>
+__global__ void __launch_bounds__(kThreads)
+    staged_tile_kernel(const C *__restrict__ src, const C *__restrict__ self_src, C *__restrict__ dst, StagedTile a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const XposeDesc &d = a.d;
+    const int lu = a.lu, lv = a.lv, lg = a.lg;
+    const int TU = 1 << lu, TV = 1 << lv, G = 1 << lg;
+    const int SV = TU + 1, SG = TV * SV + 1;
+    const int M = a.M;
+    uint32_t t = blockIdx.x;
+    const uint32_t tu = t % (uint32_t)d.tiles_u;
+    t /= (uint32_t)d.tiles_u;
+    const uint32_t tv = t % (uint32_t)d.tiles_v;
+    const uint32_t tg = t / (uint32_t)d.tiles_v;
+    const int64_t u0 = (int64_t)tu * TU, v0 = (int64_t)tv * TV, g0 = (int64_t)tg * G;
+    const int nu = (int)min<int64_t>(TU, d.Nu - u0);
+    const int nv = (int)min<int64_t>(TV, d.Nv - v0);
+    const int ng = (int)min<int64_t>(G, d.nslices - g0);
+
+    const TileLds L = tile_lds(lu, lv, lg, sizeof(C), PACK);
+    C *tile = reinterpret_cast<C *>(smem + L.tile);
+    int *gbase = reinterpret_cast<int *>(smem + L.gbase);
+    int *r0 = reinterpret_cast<int *>(smem + L.r0);
+    int *wv = reinterpret_cast<int *>(smem + L.wv);
+    int *rb = reinterpret_cast<int *>(smem + L.rb);
+    int *sb = reinterpret_cast<int *>(smem + L.sb);
+    int *kp = reinterpret_cast<int *>(smem + L.kp);
+    int *pt = reinterpret_cast<int *>(smem + L.pt);
+    int *own_a = reinterpret_cast<int *>(smem + L.own_a);
+    int *own_b = reinterpret_cast<int *>(smem + L.own_b);
+    int *mm = reinterpret_cast<int *>(smem + L.misc);  // pmin, pmax, qmin, qmax
+
+    // owners, slice bases, cleared accumulators
+    if (PACK && threadIdx.x == 0) {
+        mm[0] = INT_MAX;
+        mm[1] = -1;
+        mm[2] = INT_MAX;
+        mm[3] = -1;
+    }
+    tile_owners(d, g0, ng, u0, nu, v0, nv, own_a, own_b);
+    for (int g = threadIdx.x; g < ng; g += kThreads) {
+        int c[3];
+        int64_t ab, bb;
+        slice_coords(d, g0 + g, c, &ab, &bb);
+        gbase[g] = (int)(PACK ? ab : bb);
+    }
+    for (int i = threadIdx.x; i < G * TU; i += kThreads) {
+        r0[i] = 0;
+        wv[i] = 0;
+    }
+    if (PACK)
+        for (int i = threadIdx.x; i < kPairTab; i += kThreads) pt[i] = 0;
+    __syncthreads();
+
+    // ranks per (slice, u): one task per (entry, box of q's range); unpack also
+    // picks up q's constants, pack the span of owners in the tile
+    const int per_e = a.nbq + (PACK ? 0 : 1);
+    const int ntask = ng * nu * per_e;
+    for (int i = threadIdx.x; i < ntask; i += kThreads) {
+        const int e = i / per_e;
+        const int j = i - e * per_e;
+        const int g = e / nu, iu = e - g * nu;
+        const int k = g * TU + iu;
+        const RecvInfo &R = a.recv[own_b[k]];
+        if (j == a.nbq) {
+            rb[k] = (int)R.start;
+            sb[k] = (int)R.selfbase;
+            kp[k] = (int)R.kept;
+            continue;
+        }
+        int bc[3];
+        int64_t ab, bb;
+        slice_coords(d, g0 + g, bc, &ab, &bb);
+        int c[kMaxDims];
+#pragma unroll
+        for (int m = 0; m < kMaxDims; ++m) {
+            const int sp = a.srcpos[m];
+            c[m] = sp == 3 ? (int)v0 : sp == 4 ? (int)(u0 + iu) : sp == 0 ? bc[0] : sp == 1 ? bc[1] : bc[2];
+        }
+        const RankBox B = R.box[j];
+        const int64_t ra = box_rank(B, c, M);
+#pragma unroll
+        for (int m = 0; m < kMaxDims; ++m)
+            if (m == a.vpos) c[m] += 1;
+        const int64_t rn = box_rank(B, c, M);
+        lds_add(&r0[k], ra);
+        lds_add(&wv[k], rn - ra);
+    }
+    if (PACK) {
+        int lo = INT_MAX, hi = -1;
+        for (int i = threadIdx.x; i < ng * nv; i += kThreads) {
+            const int p = own_a[(i / nv) * TV + i % nv];
+            lo = min(lo, p);
+            hi = max(hi, p);
+        }
+        if (hi >= 0) {
+            atomicMin(&mm[0], lo);
+            atomicMax(&mm[1], hi);
+        }
+        lo = INT_MAX;
+        hi = -1;
+        for (int i = threadIdx.x; i < ng * nu; i += kThreads) {
+            const int q = own_b[(i / nu) * TU + i % nu];
+            lo = min(lo, q);
+            hi = max(hi, q);
+        }
+        if (hi >= 0) {
+            atomicMin(&mm[2], lo);
+            atomicMax(&mm[3], hi);
+        }
+    }
+    __syncthreads();
+
+    // pack: D(p, q) for every (p, q) in the tile's owner spans, one task per
+    // (pair, box) plus one for xs_p
+    const int pmin = PACK ? mm[0] : 0, qmin = PACK ? mm[2] : 0;
+    const int nq = PACK ? mm[3] - qmin + 1 : 0;
+    const bool dense = PACK && (int64_t)(mm[1] - pmin + 1) * nq <= kPairTab;
+    if (PACK && dense) {
+        const int per = a.nbp + a.nbq + 1;
+        const int n = (mm[1] - pmin + 1) * nq * per;
+        for (int i = threadIdx.x; i < n; i += kThreads) {
+            const int e = i / per, j = i - e * per;
+            const int p = pmin + e / nq, q = qmin + e % nq;
+            const SendInfo &S = a.send[p];
+            const RecvInfo &R = a.recv[q];
+            int64_t v;
+            if (j < a.nbp) {
+                const RankBox B = S.box[j];
+                v = box_rank(B, R.first_b, M);
+            } else if (j < a.nbp + a.nbq) {
+                const RankBox B = R.box[j - a.nbp];
+                v = -box_rank(B, S.first_a, M);
+            } else {
+                v = S.xs;
+            }
+            lds_add(&pt[e], v);
+        }
+        __syncthreads();
+    }
+
+    // read: every item's load is issued before any LDS store
+    {
+        C val[kTileItems];
+        int at[kTileItems];
+#pragma unroll
+        for (int j = 0; j < kTileItems; ++j) at[j] = -1;
+        const int a_sv = (int)d.a_sv;
+        tile_pass<LR>(lu, lv, lg, nu, nv, ng, [&](int j, int g, int iv, int iu) {
+            at[j] = g * SG + iv * SV + iu;
+            if (PACK) {
+                val[j] = xld(src + (gbase[g] + (int)(v0 + iv) * a_sv + (int)u0 + iu));
+            } else {
+                const int k = g * TU + iu;
+                const int p = own_a[g * TV + iv];
+                const int q = own_b[k];
+                const int rk = r0[k] + iv * wv[k];
+                const C *from = src;
+                int off;
+                if (p == q) {
+                    from = self_src;
+                    off = sb[k] + rk;
+                } else {
+                    off = rb[k] + rk - (p > q ? kp[k] : 0);
+                }
+                val[j] = (uint32_t)off < (uint32_t)a.T ? xld(from + off) : mk<C>(0, 0);
+            }
+        });
+#pragma unroll
+        for (int j = 0; j < kTileItems; ++j)
+            if (at[j] >= 0) tile[at[j]] = val[j];
+    }
+    __syncthreads();
+    // write
+    if (PACK) {
+        if (dense) {
+            tile_pass<LW>(lu, lv, lg, nu, nv, ng, [&](int, int g, int iv, int iu) {
+                const int k = g * TU + iu;
+                const int p = own_a[g * TV + iv];
+                const int q = own_b[k];
+                const int off = pt[(p - pmin) * nq + (q - qmin)] + r0[k] + iv * wv[k];
+                if ((uint32_t)off < (uint32_t)a.T) xst(dst + off, tile[g * SG + iv * SV + iu]);
+            });
+        } else {
+            tile_pass<LW>(lu, lv, lg, nu, nv, ng, [&](int, int g, int iv, int iu) {
+                const int k = g * TU + iu;
+                const int off = (int)pair_base(a, own_a[g * TV + iv], own_b[k]) + r0[k] + iv * wv[k];
+                if ((uint32_t)off < (uint32_t)a.T) xst(dst + off, tile[g * SG + iv * SV + iu]);
+            });
+        }
+    } else {
+        const int b_su = (int)d.b_su;
+        tile_pass<LW>(lu, lv, lg, nu, nv, ng, [&](int, int g, int iv, int iu) {
+            xst(dst + (gbase[g] + (int)(u0 + iu) * b_su + (int)v0 + iv), tile[g * SG + iv * SV + iu]);
+        });
+    }
+}
 
 template <class Key>
 __device__ __forceinline__ int64_t upper_index(Key key, int64_t lo, int64_t hi, int64_t x)
@@ -73,72 +436,83 @@ __device__ __forceinline__ int64_t upper_index(Key key, int64_t lo, int64_t hi, 
     return lo;
 }
 
-template <typename C, bool UNPACK>
-__global__ void __launch_bounds__(kThreads)
-    box_copy_kernel(const C *__restrict__ src, const C *__restrict__ send, C *__restrict__ dst, StagedArgs a)
-{
-    __shared__ int64_t first_box, last_box;
-    const int64_t s0 = (int64_t)blockIdx.x * kChunk;
-    const int64_t s1 = min<int64_t>(s0 + kChunk, a.total) - 1;
-    auto key = [&](int64_t i) { return UNPACK ? a.boxes[i].recv_off : a.boxes[i].send_off; };
-    if (threadIdx.x == 0) first_box = upper_index(key, 0, a.nbox - 1, s0);
-    if (threadIdx.x == 1) last_box = upper_index(key, 0, a.nbox - 1, s1);
-    __syncthreads();
-    const int64_t b_lo = first_box, b_hi = last_box;
-    for (int64_t s = s0 + threadIdx.x; s <= s1; s += kThreads) {
-        const int64_t bi = upper_index(key, b_lo, b_hi, s);
-        const BoxCopy &B = a.boxes[bi];
-        int64_t e = s - key(bi);
-        // coordinates inside the box, A's fastest axis first
-        int64_t addr_a = 0, addr_b = 0;
-        for (int i = a.M - 1; i >= 0; --i) {
-            const int ax = a.ord_a[i];
-            const int64_t c = e % B.ext[ax];
-            e /= B.ext[ax];
-            const int64_t g = B.lo[ax] + c;
-            addr_a += g * a.stride_a[ax];
-            addr_b += g * a.stride_b[ax];
-        }
-        if (!UNPACK) {
-            dst[s] = src[addr_a];  // layout A -> send array
-        } else {
-            const C v = B.self ? send[B.send_off + (s - B.recv_off)] : src[s];
-            dst[addr_b] = v;       // receive (or kept) array -> layout B
-        }
-    }
-}
+constexpr int kChunk = 4096;  // exchanged points per work-group
+constexpr int kChunkItems = kChunk / kThreads;
+constexpr int kChunkSegsLds = 512;  // segment starts of a chunk staged in LDS
 
 template <typename C>
 __global__ void __launch_bounds__(kThreads)
-    exchange_kernel(const C *__restrict__ send, C *__restrict__ recv, StagedArgs a)
+    exchange_kernel(const C *__restrict__ send, C *__restrict__ recv, ExchangeArgs a)
 {
-    __shared__ int64_t first_seg, last_seg;
+    __shared__ int64_t s_xoff[kChunkSegsLds];
+    __shared__ int copied_wg;
     const int64_t x0 = (int64_t)blockIdx.x * kChunk;
     const int64_t x1 = min<int64_t>(x0 + kChunk, a.total) - 1;
-    auto key = [&](int64_t i) { return a.segs[i].xoff; };
-    if (threadIdx.x == 0) first_seg = upper_index(key, 0, a.nseg - 1, x0);
-    if (threadIdx.x == 1) last_seg = upper_index(key, 0, a.nseg - 1, x1);
-    __syncthreads();
+    const int64_t fs = a.chunk_seg[2 * blockIdx.x], ls = a.chunk_seg[2 * blockIdx.x + 1];
+    const int n = (int)(x1 - x0 + 1);
+    if (threadIdx.x == 0) copied_wg = 0;
     int copied = 0;
-    for (int64_t x = x0 + threadIdx.x; x <= x1; x += kThreads) {
-        const int64_t si = upper_index(key, first_seg, last_seg, x);
-        const SegCopy &S = a.segs[si];
-        const int64_t o = x - S.xoff;
-        recv[S.dst + o] = send[S.src + o];
-        ++copied;
+    C v[kChunkItems];
+    if (fs == ls) {
+        // the whole chunk lies in one segment: a straight copy
+        const SegCopy S = a.segs[fs];
+        const C *from = send + S.src + (x0 - S.xoff);
+        C *to = recv + S.dst + (x0 - S.xoff);
+#pragma unroll
+        for (int j = 0; j < kChunkItems; ++j) {
+            const int i = threadIdx.x + j * kThreads;
+            if (i < n) v[j] = xld(from + i);
+        }
+#pragma unroll
+        for (int j = 0; j < kChunkItems; ++j) {
+            const int i = threadIdx.x + j * kThreads;
+            if (i < n) {
+                xst(to + i, v[j]);
+                ++copied;
+            }
+        }
+    } else {
+        // several segments: their starts in LDS when few enough
+        const int nseg = (int)(ls - fs + 1);
+        const bool in_lds = nseg <= kChunkSegsLds;
+        if (in_lds)
+            for (int i = threadIdx.x; i < nseg; i += kThreads) s_xoff[i] = a.segs[fs + i].xoff;
+        __syncthreads();
+        int64_t to[kChunkItems];
+#pragma unroll
+        for (int j = 0; j < kChunkItems; ++j) {
+            const int i = threadIdx.x + j * kThreads;
+            to[j] = -1;
+            if (i < n) {
+                const int64_t x = x0 + i;
+                int64_t si;
+                if (in_lds)
+                    si = fs + upper_index([&](int64_t m) { return s_xoff[m]; }, 0, nseg - 1, x);
+                else
+                    si = upper_index([&](int64_t m) { return a.segs[m].xoff; }, fs, ls, x);
+                const SegCopy &S = a.segs[si];
+                const int64_t o = x - S.xoff;
+                to[j] = S.dst + o;
+                v[j] = xld(send + S.src + o);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kChunkItems; ++j) {
+            if (to[j] >= 0) {
+                xst(recv + to[j], v[j]);
+                ++copied;
+            }
+        }
     }
+    __syncthreads();
     for (int off = 32; off > 0; off >>= 1) copied += __shfl_xor(copied, off);
-    if ((threadIdx.x & 63) == 0 && copied) atomicAdd(a.counter, (unsigned long long)copied);
+    if ((threadIdx.x & 63) == 0 && copied) atomicAdd(&copied_wg, copied);
+    __syncthreads();
+    if (threadIdx.x == 0 && copied_wg)
+        atomicAdd(a.counter + (blockIdx.x % kCountSlots) * kCountStride, (unsigned long long)copied_wg);
 }
 
 namespace {
-
-struct HostBox {
-    int64_t p, q;
-    int64_t seq;  // order of the box inside p's range
-    Box box;
-    int64_t n;
-};
 
 int copy_to_device(fft_plan_impl *pl, const void *h, size_t bytes, void **d)
 {
@@ -153,6 +527,156 @@ int copy_to_device(fft_plan_impl *pl, const void *h, size_t bytes, void **d)
     return FFTRW_OK;
 }
 
+int ilog2ceil(i64 n)
+{
+    int l = 0;
+    while (((i64)1 << l) < n) ++l;
+    return l;
+}
+
+// Boxes of a range in the axis order `perm`, padded to kRangeBoxes.
+void fill_boxes(const std::vector<Box> &boxes, const int *perm, int M, RankBox *out)
+{
+    for (int j = 0; j < kRangeBoxes; ++j) {
+        RankBox &rb = out[j];
+        for (int i = 0; i < kMaxDims; ++i) {
+            rb.lo[i] = INT_MAX;
+            rb.hi[i] = -1;
+            rb.suf[i] = 0;
+        }
+        if (j >= (int)boxes.size()) continue;
+        i64 suf = 1;
+        for (int i = M - 1; i >= 0; --i) {
+            const int ax = perm[i];
+            rb.lo[i] = (int)boxes[j].lo[ax];
+            rb.hi[i] = (int)boxes[j].hi[ax];
+            rb.suf[i] = suf;
+            suf *= boxes[j].hi[ax] - boxes[j].lo[ax] + 1;
+        }
+    }
+}
+
+// The natural axis along which (p, q) segments run: the innermost axis, in A's
+// order, that spans more than one value in a representative pair box (the
+// largest piece of a middle process's largest range box).
+int segment_axis(const Layout &a, const Layout &b, int M)
+{
+    const std::vector<Box> bx = range_boxes(a, a.P / 2);
+    size_t big = 0;
+    for (size_t i = 1; i < bx.size(); ++i)
+        if (box_volume(bx[i], M) > box_volume(bx[big], M)) big = i;
+    Box best = bx[big];
+    i64 bestn = -1;
+    for_each_owner(b, bx[big], [&](i64 q) {
+        for (const Box &C : range_boxes(b, q)) {
+            Box X;
+            if (box_intersect(bx[big], C, M, &X) && box_volume(X, M) > bestn) {
+                bestn = box_volume(X, M);
+                best = X;
+            }
+        }
+    });
+    for (int i = M - 1; i >= 0; --i) {
+        const int ax = a.perm[i];
+        if (best.hi[ax] > best.lo[ax]) return ax;
+    }
+    return a.perm[M - 1];
+}
+
+// A tiling for one staged kernel: the transpose's geometry with the segment
+// axis moved to the front of the batch axes (it becomes the tile's slice axis
+// when it is neither u nor v), and extents favouring the read and write axes.
+StagedTileCfg make_tile(const fft_plan_impl *pl, int t, int seg_axis, bool pack)
+{
+    const Layout &a = pl->lay[t];
+    const Layout &b = pl->lay[t + 1];
+    const int M = pl->M;
+    const int u = a.perm[M - 1], v = b.perm[M - 1];
+    StagedTileCfg c;
+    c.d = pl->xp[t];
+    XposeDesc &d = c.d;
+    // batch axes as the transpose orders them (innermost = smallest stride in A)
+    int bat[3], nb = 0;
+    for (int ax = 0; ax < M; ++ax)
+        if (ax != u && ax != v) bat[nb++] = ax;
+    std::sort(bat, bat + nb, [&](int x, int y) { return a.stride[x] < a.stride[y]; });
+    int order[3] = {0, 1, 2};  // new batch index -> old
+    const int sa = (seg_axis != u && seg_axis != v) ? seg_axis : -1;
+    if (sa >= 0) {
+        int j = 0;
+        while (bat[j] != sa) ++j;
+        for (int i = j; i > 0; --i) order[i] = order[i - 1];
+        order[0] = j;
+    }
+    int newidx[3] = {0, 1, 2};
+    const XposeDesc o = d;
+    for (int i = 0; i < nb; ++i) {
+        d.bsize[i] = o.bsize[order[i]];
+        d.ba[i] = o.ba[order[i]];
+        d.bb[i] = o.bb[order[i]];
+        newidx[order[i]] = i;
+    }
+    for (int j = 0; j < d.ka; ++j)
+        if (d.srca[j] < 3) d.srca[j] = newidx[o.srca[j]];
+    for (int j = 0; j < d.kb; ++j)
+        if (d.srcb[j] < 3) d.srcb[j] = newidx[o.srcb[j]];
+    for (int i = 0; i < M; ++i) {
+        const int ax = a.perm[i];
+        if (ax == u)
+            c.srcpos[i] = 4;
+        else if (ax == v) {
+            c.srcpos[i] = 3;
+            c.vpos = i;
+        } else {
+            int j = 0;
+            while (bat[j] != ax) ++j;
+            c.srcpos[i] = newidx[j];
+        }
+    }
+    // extents: the read and write axes first, then fill up to the budget;
+    // each axis at most 256 (one lane pass), slices x u at most 512 (tables)
+    const int budget = pl->esz == 8 ? 11 : 10;
+    const int cap[3] = {std::min(8, ilog2ceil(d.Nu)), std::min(8, ilog2ceil(d.Nv)),
+                        nb ? std::min(8, ilog2ceil(d.bsize[0])) : 0};
+    int l[3] = {0, 0, 0};
+    auto room = [&](int ax) {
+        int r = std::max(0, budget - l[0] - l[1] - l[2]);
+        if (ax != 1) r = std::min(r, std::max(0, 9 - l[0] - l[2]));
+        return r;
+    };
+    auto want = [&](int ax, int lg2) { l[ax] = std::min(cap[ax], std::max(l[ax], std::min(lg2, l[ax] + room(ax)))); };
+    auto fill = [&](int ax) { l[ax] = std::min(cap[ax], l[ax] + room(ax)); };
+    const int f = seg_axis == u ? 0 : (seg_axis == v ? 1 : 2);
+    c.lane_r = pack ? 0 : f;
+    c.lane_w = pack ? f : 1;
+    const int ra = c.lane_r, wa = c.lane_w;
+    if (ra == wa) {
+        want(ra, 6);
+    } else if (ra != 2 && wa != 2) {
+        want(ra, (budget + 1) / 2);
+        want(wa, budget / 2);
+    } else {
+        want(ra == 2 ? wa : ra, 4);
+        want(2, 5);
+    }
+    fill(1);
+    fill(0);
+    fill(2);
+    c.lu = l[0];
+    c.lv = l[1];
+    c.lg = l[2];
+    d.TU = 1 << c.lu;
+    d.TV = 1 << c.lv;
+    d.G = 1 << c.lg;
+    d.tiles_u = (d.Nu + d.TU - 1) / d.TU;
+    d.tiles_v = (d.Nv + d.TV - 1) / d.TV;
+    d.tiles_g = (d.nslices + d.G - 1) / d.G;
+    d.count = 1;
+    d.counter = nullptr;
+    d.mu = nullptr;
+    return c;
+}
+
 }  // namespace
 
 int staged_build(fft_plan_impl *pl, int t)
@@ -162,6 +686,11 @@ int staged_build(fft_plan_impl *pl, int t)
     const Layout &a = pl->lay[t];
     const Layout &b = pl->lay[t + 1];
     const int M = pl->M;
+    const i64 P = pl->P;
+    if (a.row_split() || b.row_split())
+        return fail(FFTRW_E_ROWSPLIT, "staged transposes need whole rows in both decompositions");
+    if (pl->T >= ((i64)1 << 31) || P >= ((i64)1 << 31))
+        return fail(FFTRW_E_SIZE, "staged transposes support fewer than 2^31 points");
     if (!pl->send) {
         for (void **buf : {&pl->send, &pl->recv}) {
             if (hipMalloc(buf, (size_t)pl->T * pl->esz) != hipSuccess) {
@@ -171,142 +700,188 @@ int staged_build(fft_plan_impl *pl, int t)
             pl->dev_bytes += (size_t)pl->T * pl->esz;
         }
     }
-    // every (p, q) box, in p's range order
-    std::vector<HostBox> hb;
-    for (int64_t p = 0; p < a.P; ++p) {
-        int64_t seq = 0;
-        for (const Box &B : range_boxes(a, p)) {
-            for_each_owner(b, B, [&](int64_t q) {
-                for (const Box &Cq : range_boxes(b, q)) {
-                    Box X;
-                    if (box_intersect(B, Cq, M, &X)) hb.push_back({p, q, seq++, X, box_volume(X, M)});
-                }
-            });
-        }
-    }
-    // send order: (p, q, seq); a process's send array starts at its range start
-    std::stable_sort(hb.begin(), hb.end(), [](const HostBox &x, const HostBox &y) {
-        return x.p != y.p ? x.p < y.p : (x.q != y.q ? x.q < y.q : x.seq < y.seq);
-    });
-    std::vector<BoxCopy> boxes(hb.size());
-    std::vector<int64_t> seg_send;  // per box: offset of its (p,q) segment start
-    {
-        int64_t pos = 0;
-        for (size_t i = 0; i < hb.size(); ++i) {
-            BoxCopy &bc = boxes[i];
-            for (int d = 0; d < kMaxDims; ++d) {
-                bc.lo[d] = d < M ? (int)hb[i].box.lo[d] : 0;
-                bc.ext[d] = d < M ? (int)(hb[i].box.hi[d] - hb[i].box.lo[d] + 1) : 1;
-            }
-            bc.send_off = pos;
-            bc.self = hb[i].p == hb[i].q;
-            bc.pad = 0;
-            pos += hb[i].n;
-        }
-        if (pos != pl->T) return fail(FFTRW_E_DEVICE, "internal: staged boxes do not cover the array");
-    }
-    // receive order: (q, p, seq)
-    std::vector<size_t> ridx(hb.size());
-    for (size_t i = 0; i < ridx.size(); ++i) ridx[i] = i;
-    std::stable_sort(ridx.begin(), ridx.end(), [&](size_t x, size_t y) {
-        const HostBox &X = hb[x], &Y = hb[y];
-        return X.q != Y.q ? X.q < Y.q : (X.p != Y.p ? X.p < Y.p : X.seq < Y.seq);
-    });
-    {
-        int64_t pos = 0;
-        for (size_t r : ridx) {
-            boxes[r].recv_off = pos;
-            pos += hb[r].n;
-        }
-    }
-    // exchanged segments: maximal runs of boxes with the same (p, q), p != q;
-    // in both orders the boxes of one segment are consecutive
+    // every (p, q) pair that shares points, by p then q
+    const std::vector<PairCount> pc = pair_counts(a, b);
+    std::vector<RecvInfo> ri(P);
+    std::vector<SendInfo> si(P);
+    std::vector<i64> before_q(P, 0);   // points of Q_q in the ranges of sources < p
+    std::vector<i64> recv_fill(P, 0);  // received points of q so far (sources != q)
     std::vector<SegCopy> segs;
-    int64_t moved = 0;
-    for (size_t i = 0; i < hb.size();) {
-        size_t j = i;
-        int64_t len = 0;
-        while (j < hb.size() && hb[j].p == hb[i].p && hb[j].q == hb[i].q) len += hb[j++].n;
-        if (hb[i].p != hb[i].q) {
-            segs.push_back({moved, boxes[i].send_off, boxes[i].recv_off, len});
-            moved += len;
+    i64 moved = 0;
+    {
+        size_t i = 0;
+        for (i64 p = 0; p < P; ++p) {
+            const i64 xs = a.boundary(p);
+            i64 segoff = 0;
+            for (; i < pc.size() && pc[i].p == p; ++i) {
+                const i64 q = pc[i].q, n = pc[i].n;
+                if (p == q) {
+                    ri[q].kept = n;
+                    ri[q].selfbase = xs + segoff - before_q[q];
+                } else {
+                    segs.push_back({moved, xs + segoff, b.boundary(q) + recv_fill[q], n});
+                    moved += n;
+                    recv_fill[q] += n;
+                }
+                before_q[q] += n;
+                segoff += n;
+            }
+            if (segoff != a.boundary(p + 1) - xs)
+                return fail(FFTRW_E_DEVICE, "internal: staged pairs do not cover a range");
         }
-        i = j;
     }
-    std::vector<BoxCopy> boxes_recv(hb.size());
-    for (size_t k = 0; k < ridx.size(); ++k) boxes_recv[k] = boxes[ridx[k]];
+    // ranges as boxes: destinations in A's order, sources in B's order
+    int nbp = 0, nbq = 0;
+    for (i64 q = 0; q < P; ++q) {
+        RecvInfo &r = ri[q];
+        r.start = b.boundary(q);
+        i64 st[kMaxDims];
+        range_of(b, q, nullptr, nullptr, st, nullptr);
+        for (int i = 0; i < kMaxDims; ++i) r.first_b[i] = i < M ? (int)st[i] : 0;
+        r.pad = 0;
+        const std::vector<Box> boxes = range_boxes(b, q);
+        if ((int)boxes.size() > kRangeBoxes) return fail(FFTRW_E_DEVICE, "internal: too many range boxes");
+        nbq = std::max(nbq, (int)boxes.size());
+        fill_boxes(boxes, a.perm, M, r.box);
+    }
+    for (i64 p = 0; p < P; ++p) {
+        SendInfo &s = si[p];
+        s.xs = a.boundary(p);
+        i64 st[kMaxDims];
+        range_of(a, p, nullptr, nullptr, st, nullptr);
+        for (int i = 0; i < kMaxDims; ++i) s.first_a[i] = i < M ? (int)st[i] : 0;
+        s.pad = 0;
+        const std::vector<Box> boxes = range_boxes(a, p);
+        if ((int)boxes.size() > kRangeBoxes) return fail(FFTRW_E_DEVICE, "internal: too many range boxes");
+        nbp = std::max(nbp, (int)boxes.size());
+        fill_boxes(boxes, b.perm, M, s.box);
+    }
 
     StagedStep &st = pl->staged[t];
-    st.nbox = (int64_t)boxes.size();
+    st.npair = (int64_t)pc.size();
     st.nseg = (int64_t)segs.size();
     st.seg_elems = moved;
-    int rc = copy_to_device(pl, boxes.data(), sizeof(BoxCopy) * boxes.size(), &st.boxes);
-    if (!rc) rc = copy_to_device(pl, boxes_recv.data(), sizeof(BoxCopy) * boxes_recv.size(), &st.pack_prefix);
+    st.nbp = nbp;
+    st.nbq = nbq;
+    st.seg_axis = segment_axis(a, b, M);
+    st.pack = make_tile(pl, t, st.seg_axis, true);
+    st.unpack = make_tile(pl, t, st.seg_axis, false);
+    for (const StagedTileCfg *c : {&st.pack, &st.unpack}) {
+        if (c->d.tiles_u * c->d.tiles_v * c->d.tiles_g >= (i64)0x7fffffff)
+            return fail(FFTRW_E_SIZE, "array too large for one staged launch");
+        if (c->lu + c->lv + c->lg > 12 || c->lu + c->lg > 9 || c->lu > 8 || c->lv > 8 || c->lg > 8)
+            return fail(FFTRW_E_DEVICE, "internal: staged tile exceeds its LDS tables");
+    }
+    // first and last segment of every exchange chunk
+    std::vector<int64_t> chunk_seg;
+    {
+        const i64 nch = (moved + kChunk - 1) / kChunk;
+        chunk_seg.resize(2 * (size_t)nch);
+        size_t j = 0;
+        for (i64 c = 0; c < nch; ++c) {
+            const i64 x0 = c * kChunk, x1 = std::min<i64>(x0 + kChunk, moved) - 1;
+            while (j + 1 < segs.size() && segs[j + 1].xoff <= x0) ++j;
+            size_t k = j;
+            while (k + 1 < segs.size() && segs[k + 1].xoff <= x1) ++k;
+            chunk_seg[2 * c] = (int64_t)j;
+            chunk_seg[2 * c + 1] = (int64_t)k;
+        }
+    }
+    int rc = copy_to_device(pl, ri.data(), sizeof(RecvInfo) * ri.size(), &st.recv_info);
+    if (!rc) rc = copy_to_device(pl, si.data(), sizeof(SendInfo) * si.size(), &st.send_info);
     if (!rc) rc = copy_to_device(pl, segs.data(), sizeof(SegCopy) * segs.size(), &st.segs);
+    if (!rc) rc = copy_to_device(pl, chunk_seg.data(), sizeof(int64_t) * chunk_seg.size(), &st.chunk_seg);
     return rc;
 }
+
+namespace {
+
+StagedTile tile_args(const fft_plan_impl *pl, const StagedStep &st, const StagedTileCfg &c)
+{
+    StagedTile g;
+    std::memset(&g, 0, sizeof(g));
+    g.d = c.d;
+    g.lu = c.lu;
+    g.lv = c.lv;
+    g.lg = c.lg;
+    g.lane_r = c.lane_r;
+    g.lane_w = c.lane_w;
+    g.M = pl->M;
+    g.nbp = st.nbp;
+    g.nbq = st.nbq;
+    for (int i = 0; i < kMaxDims; ++i) g.srcpos[i] = c.srcpos[i];
+    g.vpos = c.vpos;
+    g.T = pl->T;
+    g.recv = (const RecvInfo *)st.recv_info;
+    g.send = (const SendInfo *)st.send_info;
+    return g;
+}
+
+template <typename C>
+hipError_t launch_staged(const fft_plan_impl *pl, const StagedStep &st, const void *in, void *out, hipStream_t s, int t)
+{
+    // pack: layout A -> send array
+    {
+        const StagedTile g = tile_args(pl, st, st.pack);
+        const size_t lds = tile_lds(g.lu, g.lv, g.lg, sizeof(C), true).total;
+        const unsigned n = (unsigned)(g.d.tiles_u * g.d.tiles_v * g.d.tiles_g);
+        const C *i = (const C *)in;
+        C *o = (C *)pl->send;
+        if (g.lane_w == 0)
+            hipLaunchKernelGGL((staged_tile_kernel<C, true, 0, 0>), dim3(n), dim3(kThreads), lds, s, i, i, o, g);
+        else if (g.lane_w == 1)
+            hipLaunchKernelGGL((staged_tile_kernel<C, true, 0, 1>), dim3(n), dim3(kThreads), lds, s, i, i, o, g);
+        else
+            hipLaunchKernelGGL((staged_tile_kernel<C, true, 0, 2>), dim3(n), dim3(kThreads), lds, s, i, i, o, g);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // exchange: only segments between different processes
+    if (st.seg_elems > 0) {
+        ExchangeArgs x;
+        x.segs = (const SegCopy *)st.segs;
+        x.chunk_seg = (const int64_t *)st.chunk_seg;
+        x.nseg = st.nseg;
+        x.total = st.seg_elems;
+        x.counter = pl->counters + (size_t)t * kCountBlock;
+        const unsigned xb = (unsigned)((st.seg_elems + kChunk - 1) / kChunk);
+        hipLaunchKernelGGL(exchange_kernel<C>, dim3(xb), dim3(kThreads), 0, s, (const C *)pl->send, (C *)pl->recv,
+                           x);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // unpack: receive array (and kept segments) -> layout B
+    {
+        const StagedTile g = tile_args(pl, st, st.unpack);
+        const size_t lds = tile_lds(g.lu, g.lv, g.lg, sizeof(C), false).total;
+        const unsigned n = (unsigned)(g.d.tiles_u * g.d.tiles_v * g.d.tiles_g);
+        const C *r = (const C *)pl->recv, *sd = (const C *)pl->send;
+        C *o = (C *)out;
+        if (g.lane_r == 0)
+            hipLaunchKernelGGL((staged_tile_kernel<C, false, 0, 1>), dim3(n), dim3(kThreads), lds, s, r, sd, o, g);
+        else if (g.lane_r == 1)
+            hipLaunchKernelGGL((staged_tile_kernel<C, false, 1, 1>), dim3(n), dim3(kThreads), lds, s, r, sd, o, g);
+        else
+            hipLaunchKernelGGL((staged_tile_kernel<C, false, 2, 1>), dim3(n), dim3(kThreads), lds, s, r, sd, o, g);
+        return hipGetLastError();
+    }
+}
+
+}  // namespace
 
 int staged_run(fft_plan_impl *pl, int t, const void *in, void *out, hipStream_t s)
 {
     const StagedStep &st = pl->staged[t];
-    const Layout &a = pl->lay[t];
-    const Layout &b = pl->lay[t + 1];
-    StagedArgs g;
-    std::memset(&g, 0, sizeof(g));
-    g.M = pl->M;
-    for (int i = 0; i < pl->M; ++i) {
-        g.ord_a[i] = a.perm[i];
-        g.stride_a[i] = a.stride[i];
-        g.stride_b[i] = b.stride[i];
-    }
-    g.nbox = st.nbox;
-    g.total = pl->T;
-    g.counter = pl->counters + t;
-    const unsigned nblk = (unsigned)((pl->T + kChunk - 1) / kChunk);
-    const bool fp64 = pl->esz == 16;
-    // pack: layout A -> send array
-    g.boxes = (const BoxCopy *)st.boxes;
-    if (fp64)
-        hipLaunchKernelGGL((box_copy_kernel<double2, false>), dim3(nblk), dim3(kThreads), 0, s,
-                           (const double2 *)in, (const double2 *)nullptr, (double2 *)pl->send, g);
-    else
-        hipLaunchKernelGGL((box_copy_kernel<float2, false>), dim3(nblk), dim3(kThreads), 0, s,
-                           (const float2 *)in, (const float2 *)nullptr, (float2 *)pl->send, g);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(FFTRW_E_DEVICE, std::string("pack launch: ") + hipGetErrorString(e));
-    // exchange: only segments between different processes
-    if (st.seg_elems > 0) {
-        StagedArgs x = g;
-        x.segs = (const SegCopy *)st.segs;
-        x.nseg = st.nseg;
-        x.total = st.seg_elems;
-        const unsigned xb = (unsigned)((st.seg_elems + kChunk - 1) / kChunk);
-        if (fp64)
-            hipLaunchKernelGGL(exchange_kernel<double2>, dim3(xb), dim3(kThreads), 0, s,
-                               (const double2 *)pl->send, (double2 *)pl->recv, x);
-        else
-            hipLaunchKernelGGL(exchange_kernel<float2>, dim3(xb), dim3(kThreads), 0, s,
-                               (const float2 *)pl->send, (float2 *)pl->recv, x);
-        e = hipGetLastError();
-        if (e != hipSuccess) return fail(FFTRW_E_DEVICE, std::string("exchange launch: ") + hipGetErrorString(e));
-    }
-    // unpack: receive array (and kept segments) -> layout B
-    g.boxes = (const BoxCopy *)st.pack_prefix;
-    if (fp64)
-        hipLaunchKernelGGL((box_copy_kernel<double2, true>), dim3(nblk), dim3(kThreads), 0, s,
-                           (const double2 *)pl->recv, (const double2 *)pl->send, (double2 *)out, g);
-    else
-        hipLaunchKernelGGL((box_copy_kernel<float2, true>), dim3(nblk), dim3(kThreads), 0, s,
-                           (const float2 *)pl->recv, (const float2 *)pl->send, (float2 *)out, g);
-    e = hipGetLastError();
-    if (e != hipSuccess) return fail(FFTRW_E_DEVICE, std::string("unpack launch: ") + hipGetErrorString(e));
+    const hipError_t e = pl->esz == 16 ? launch_staged<double2>(pl, st, in, out, s, t)
+                                       : launch_staged<float2>(pl, st, in, out, s, t);
+    if (e != hipSuccess) return fail(FFTRW_E_DEVICE, std::string("staged transpose launch: ") + hipGetErrorString(e));
     return FFTRW_OK;
 }
 
 void staged_free(fft_plan_impl *pl)
 {
     for (StagedStep &st : pl->staged) {
-        for (void *p : {st.boxes, st.pack_prefix, st.unpack_prefix, st.segs, st.seg_prefix})
+        for (void *p : {st.recv_info, st.send_info, st.segs, st.chunk_seg})
             if (p) (void)hipFree(p);
         st = StagedStep{};
     }

@@ -75,6 +75,40 @@ __device__ __forceinline__ void slice_coords(const XposeDesc &d, int64_t s, int 
     *bb = b;
 }
 
+// Owner vectors of one tile: A's over (slice, v) into own_a[g * TV + iv], B's
+// over (slice, u) into own_b[g * TU + iu] (slices g0 .. g0 + ng - 1).
+__device__ __forceinline__ void tile_owners(const XposeDesc &d, int64_t g0, int ng, int64_t u0, int nu, int64_t v0,
+                                            int nv, int *own_a, int *own_b)
+{
+    const bool narrow = d.owner32 != 0;
+    for (int i = threadIdx.x; i < ng * nv; i += kThreads) {
+        const int g = i / nv, iv = i - g * nv;
+        int c[3];
+        int64_t ab, bb;
+        slice_coords(d, g0 + g, c, &ab, &bb);
+        int64_t r = 0;
+        for (int j = 0; j < d.ka; ++j) {
+            const int src = d.srca[j];
+            r += (src == 3 ? v0 + iv : (int64_t)c[src]) * d.wa[j];
+        }
+        int64_t o = owner_of_row(r, d.P, d.Ra, narrow);
+        if (d.mu) o = d.mu[o];
+        own_a[g * d.TV + iv] = (int)o;
+    }
+    for (int i = threadIdx.x; i < ng * nu; i += kThreads) {
+        const int g = i / nu, iu = i - g * nu;
+        int c[3];
+        int64_t ab, bb;
+        slice_coords(d, g0 + g, c, &ab, &bb);
+        int64_t r = 0;
+        for (int j = 0; j < d.kb; ++j) {
+            const int src = d.srcb[j];
+            r += (src == 4 ? u0 + iu : (int64_t)c[src]) * d.wb[j];
+        }
+        own_b[g * d.TU + iu] = (int)owner_of_row(r, d.P, d.Rb, narrow);
+    }
+}
+
 // LDS bytes of a tile (and the owner vectors when counting), 16-byte aligned
 __host__ __device__ inline size_t xpose_tile_bytes(const XposeDesc &d, size_t esz)
 {
@@ -108,34 +142,7 @@ __device__ __forceinline__ void xpose_tile(const C *__restrict__ in, C *__restri
     int *own_b = own_a + d.G * TV;
     if (d.count) {
         if (threadIdx.x == 0) moved_wg = 0;
-        // owner vectors: A's over (slice, v), B's over (slice, u)
-        const bool narrow = d.owner32 != 0;
-        for (int i = threadIdx.x; i < ng * nv; i += kThreads) {
-            const int g = i / nv, iv = i - g * nv;
-            int c[3];
-            int64_t ab, bb;
-            slice_coords(d, g0 + g, c, &ab, &bb);
-            int64_t r = 0;
-            for (int j = 0; j < d.ka; ++j) {
-                const int src = d.srca[j];
-                r += (src == 3 ? v0 + iv : (int64_t)c[src]) * d.wa[j];
-            }
-            int64_t o = owner_of_row(r, d.P, d.Ra, narrow);
-            if (d.mu) o = d.mu[o];
-            own_a[g * TV + iv] = (int)o;
-        }
-        for (int i = threadIdx.x; i < ng * nu; i += kThreads) {
-            const int g = i / nu, iu = i - g * nu;
-            int c[3];
-            int64_t ab, bb;
-            slice_coords(d, g0 + g, c, &ab, &bb);
-            int64_t r = 0;
-            for (int j = 0; j < d.kb; ++j) {
-                const int src = d.srcb[j];
-                r += (src == 4 ? u0 + iu : (int64_t)c[src]) * d.wb[j];
-            }
-            own_b[g * TU + iu] = (int)owner_of_row(r, d.P, d.Rb, narrow);
-        }
+        tile_owners(d, g0, ng, u0, nu, v0, nv, own_a, own_b);
     }
 
     // load: rows (g, v) of contiguous u-values
@@ -214,7 +221,8 @@ __device__ __forceinline__ void xpose_tile(const C *__restrict__ in, C *__restri
         for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
         if ((threadIdx.x & 63) == 0 && moved) atomicAdd(&moved_wg, moved);
         __syncthreads();
-        if (threadIdx.x == 0 && moved_wg) atomicAdd(d.counter, (unsigned long long)moved_wg);
+        if (threadIdx.x == 0 && moved_wg)
+            atomicAdd(d.counter + (tile_index % kCountSlots) * kCountStride, (unsigned long long)moved_wg);
     }
     __syncthreads();  // the LDS block may be reused by the caller's next unit
 }

@@ -139,11 +139,13 @@ def test_in_place_and_leave_permuted(gpu_lib, staged):
                                          ((64, 64, 64, 64), 1000, 1295),
                                          ((32, 32, 32, 32, 16), 48, 0), ((32, 32, 32, 32, 16), 256, 3333333),
                                          ((32, 32, 32, 32, 16), 1000, 7962623)])
-def test_config3_orders(gpu_lib, dims, P, oidx):
+@pytest.mark.parametrize("staged", [False, True])
+def test_config3_orders(gpu_lib, dims, P, oidx, staged):
     M = len(dims)
     order = fftrw.fft_order_at(M, oidx)
+    extra = fftrw.FLAG_STAGED if staged else 0
     try:
-        plan = fftrw.Plan(dims, P, order, flags=fftrw.FLAG_COUNT_MOVED)
+        plan = fftrw.Plan(dims, P, order, flags=fftrw.FLAG_COUNT_MOVED | extra)
     except fftrw.FftrwError as e:
         assert e.code == fftrw.E_ROWSPLIT
         pytest.skip("row-split order")
