@@ -228,6 +228,15 @@ int fft_exec_transpose(fft_plan_t plan, int t, const void *in, void *out,
 int fft_plan_stats(fft_plan_t plan, int64_t *per_step, int64_t *moved);
 
 /*
+ * fft_plan_messages -- for a plan built with FFTRW_FLAG_STAGED, the number of
+ * messages of each transpose's all-to-all: the (p, q) pairs with p != q that
+ * exchange at least one point (Fig. 4's transposes, as a distributed run
+ * would send them).  per_step[M] receives transposes 1..M-1 then the return
+ * transpose.  FFTRW_E_UNSUPPORTED for plans without staged tables.
+ */
+int fft_plan_messages(fft_plan_t plan, int64_t *per_step);
+
+/*
  * fft_plan_set_timing -- when enable != 0, every later exec records a HIP
  * event on its stream after each stage (FFT step or transpose), so
  * fft_plan_timings can report per-stage durations.  Creates the events on the
@@ -239,6 +248,9 @@ int fft_plan_set_timing(fft_plan_t plan, int enable);
  * fft_plan_timings -- durations in milliseconds of the stages of the last
  * exec with timing enabled, in launch order: FFT step 1, transpose 1, FFT
  * step 2, ..., FFT step M, return transpose (absent with LEAVE_PERMUTED).
+ * With FFTRW_FLAG_STAGED each transpose is three stages: pack, exchange,
+ * unpack.  With FFTRW_FLAG_FUSED_FFT (when the plan fuses) each stage is one
+ * FFT step together with the transpose that follows it.
  * ms: host array of capacity `cap`; *n receives the number of stages.
  * Synchronises on the last event.
  */

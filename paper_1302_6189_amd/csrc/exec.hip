@@ -41,6 +41,7 @@ size_t xpose_lds_bytes(const XposeDesc &d, size_t esz);
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 int staged_build(fft_plan_impl *pl, int t);
 int staged_run(fft_plan_impl *pl, int t, const void *in, void *out, hipStream_t s);
+int staged_part(fft_plan_impl *pl, int t, int part, const void *in, void *out, hipStream_t s);
 void staged_free(fft_plan_impl *pl);
 
 namespace {
@@ -325,8 +326,17 @@ int run_pipeline(fft_plan_impl *pl, const void *in, void *out, hipStream_t s, in
         int rc = run_fft_step(pl, t, dir, t == 0 ? in : cur, cur, scale, s);
         if (rc || (rc = mark())) return rc;
         if (t < nx) {
-            rc = run_transpose(pl, t, cur, other, s);
-            if (rc || (rc = mark())) return rc;
+            if (pl->timing && (pl->flags & FFTRW_FLAG_STAGED)) {
+                // pack, exchange and unpack as stages of their own
+                for (int part = 0; part < 3 && !rc; ++part) {
+                    rc = staged_part(pl, t, part, cur, other, s);
+                    if (!rc) rc = mark();
+                }
+                if (rc) return rc;
+            } else {
+                rc = run_transpose(pl, t, cur, other, s);
+                if (rc || (rc = mark())) return rc;
+            }
             std::swap(cur, other);
         }
     }
@@ -589,12 +599,21 @@ int fft_plan_stats(fft_plan_t plan, int64_t *per_step, int64_t *moved)
     return FFTRW_OK;
 }
 
+int fft_plan_messages(fft_plan_t plan, int64_t *per_step)
+{
+    g_last_error.clear();
+    if (!plan || !per_step) return fail(FFTRW_E_ARG, "null plan or output");
+    if (!(plan->flags & FFTRW_FLAG_STAGED)) return fail(FFTRW_E_UNSUPPORTED, "the plan has no staged tables");
+    for (int t = 0; t < plan->M; ++t) per_step[t] = plan->staged[t].nseg;
+    return FFTRW_OK;
+}
+
 int fft_plan_set_timing(fft_plan_t plan, int enable)
 {
     g_last_error.clear();
     if (!plan) return fail(FFTRW_E_ARG, "null plan");
     if (enable && plan->events.empty()) {
-        plan->events.resize(2 * plan->M + 1);
+        plan->events.resize(4 * plan->M + 1);
         for (hipEvent_t &e : plan->events)
             if (hipEventCreate(&e) != hipSuccess) return fail(FFTRW_E_DEVICE, "hipEventCreate failed");
     }

@@ -817,11 +817,13 @@ StagedTile tile_args(const fft_plan_impl *pl, const StagedStep &st, const Staged
     return g;
 }
 
+// part 0: pack (layout A -> send array), 1: exchange (only segments between
+// different processes), 2: unpack (receive array and kept segments -> layout B)
 template <typename C>
-hipError_t launch_staged(const fft_plan_impl *pl, const StagedStep &st, const void *in, void *out, hipStream_t s, int t)
+hipError_t launch_staged(const fft_plan_impl *pl, const StagedStep &st, int part, const void *in, void *out,
+                         hipStream_t s, int t)
 {
-    // pack: layout A -> send array
-    {
+    if (part == 0) {
         const StagedTile g = tile_args(pl, st, st.pack);
         const size_t lds = tile_lds(g.lu, g.lv, g.lg, sizeof(C), true).total;
         const unsigned n = (unsigned)(g.d.tiles_u * g.d.tiles_v * g.d.tiles_g);
@@ -833,11 +835,10 @@ hipError_t launch_staged(const fft_plan_impl *pl, const StagedStep &st, const vo
             hipLaunchKernelGGL((staged_tile_kernel<C, true, 0, 1>), dim3(n), dim3(kThreads), lds, s, i, i, o, g);
         else
             hipLaunchKernelGGL((staged_tile_kernel<C, true, 0, 2>), dim3(n), dim3(kThreads), lds, s, i, i, o, g);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        return hipGetLastError();
     }
-    // exchange: only segments between different processes
-    if (st.seg_elems > 0) {
+    if (part == 1) {
+        if (st.seg_elems == 0) return hipSuccess;
         ExchangeArgs x;
         x.segs = (const SegCopy *)st.segs;
         x.chunk_seg = (const int64_t *)st.chunk_seg;
@@ -847,34 +848,37 @@ hipError_t launch_staged(const fft_plan_impl *pl, const StagedStep &st, const vo
         const unsigned xb = (unsigned)((st.seg_elems + kChunk - 1) / kChunk);
         hipLaunchKernelGGL(exchange_kernel<C>, dim3(xb), dim3(kThreads), 0, s, (const C *)pl->send, (C *)pl->recv,
                            x);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    // unpack: receive array (and kept segments) -> layout B
-    {
-        const StagedTile g = tile_args(pl, st, st.unpack);
-        const size_t lds = tile_lds(g.lu, g.lv, g.lg, sizeof(C), false).total;
-        const unsigned n = (unsigned)(g.d.tiles_u * g.d.tiles_v * g.d.tiles_g);
-        const C *r = (const C *)pl->recv, *sd = (const C *)pl->send;
-        C *o = (C *)out;
-        if (g.lane_r == 0)
-            hipLaunchKernelGGL((staged_tile_kernel<C, false, 0, 1>), dim3(n), dim3(kThreads), lds, s, r, sd, o, g);
-        else if (g.lane_r == 1)
-            hipLaunchKernelGGL((staged_tile_kernel<C, false, 1, 1>), dim3(n), dim3(kThreads), lds, s, r, sd, o, g);
-        else
-            hipLaunchKernelGGL((staged_tile_kernel<C, false, 2, 1>), dim3(n), dim3(kThreads), lds, s, r, sd, o, g);
         return hipGetLastError();
     }
+    const StagedTile g = tile_args(pl, st, st.unpack);
+    const size_t lds = tile_lds(g.lu, g.lv, g.lg, sizeof(C), false).total;
+    const unsigned n = (unsigned)(g.d.tiles_u * g.d.tiles_v * g.d.tiles_g);
+    const C *r = (const C *)pl->recv, *sd = (const C *)pl->send;
+    C *o = (C *)out;
+    if (g.lane_r == 0)
+        hipLaunchKernelGGL((staged_tile_kernel<C, false, 0, 1>), dim3(n), dim3(kThreads), lds, s, r, sd, o, g);
+    else if (g.lane_r == 1)
+        hipLaunchKernelGGL((staged_tile_kernel<C, false, 1, 1>), dim3(n), dim3(kThreads), lds, s, r, sd, o, g);
+    else
+        hipLaunchKernelGGL((staged_tile_kernel<C, false, 2, 1>), dim3(n), dim3(kThreads), lds, s, r, sd, o, g);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-int staged_run(fft_plan_impl *pl, int t, const void *in, void *out, hipStream_t s)
+int staged_part(fft_plan_impl *pl, int t, int part, const void *in, void *out, hipStream_t s)
 {
     const StagedStep &st = pl->staged[t];
-    const hipError_t e = pl->esz == 16 ? launch_staged<double2>(pl, st, in, out, s, t)
-                                       : launch_staged<float2>(pl, st, in, out, s, t);
+    const hipError_t e = pl->esz == 16 ? launch_staged<double2>(pl, st, part, in, out, s, t)
+                                       : launch_staged<float2>(pl, st, part, in, out, s, t);
     if (e != hipSuccess) return fail(FFTRW_E_DEVICE, std::string("staged transpose launch: ") + hipGetErrorString(e));
+    return FFTRW_OK;
+}
+
+int staged_run(fft_plan_impl *pl, int t, const void *in, void *out, hipStream_t s)
+{
+    for (int part = 0; part < 3; ++part)
+        if (int rc = staged_part(pl, t, part, in, out, s)) return rc;
     return FFTRW_OK;
 }
 

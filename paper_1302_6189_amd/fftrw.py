@@ -67,6 +67,7 @@ _SIGNATURES = {
     "fft_exec_fft_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "fft_exec_transpose": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     "fft_plan_stats": (ctypes.c_int, [_vp, _i64p, _i64p]),
+    "fft_plan_messages": (ctypes.c_int, [_vp, _i64p]),
     "fft_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "fft_plan_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
     "fft_plan_timings": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int,
@@ -283,11 +284,18 @@ class Plan:
     def set_timing(self, enable=True):
         _check(lib().fft_plan_set_timing(self._h, 1 if enable else 0))
 
+    def messages(self):
+        """Messages of each staged transpose: (p, q) pairs, p != q, that exchange points."""
+        out = (ctypes.c_int64 * self.M)()
+        _check(lib().fft_plan_messages(self._h, out))
+        return list(out)
+
     def timings(self):
-        """Per-stage durations (ms) of the last exec: FFT 1, transpose 1, ..."""
-        buf = (ctypes.c_float * (2 * self.M + 1))()
+        """Per-stage durations (ms) of the last exec: FFT 1, transpose 1, ...
+        (a staged transpose is three stages: pack, exchange, unpack)."""
+        buf = (ctypes.c_float * (4 * self.M + 1))()
         n = ctypes.c_int()
-        _check(lib().fft_plan_timings(self._h, buf, 2 * self.M + 1, ctypes.byref(n)))
+        _check(lib().fft_plan_timings(self._h, buf, 4 * self.M + 1, ctypes.byref(n)))
         return list(buf)[:n.value]
 
     def workspace_bytes(self):

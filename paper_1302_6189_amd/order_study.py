@@ -106,6 +106,20 @@ def linear_fit(v, t):
     return out
 
 
+def two_term_fit(v, n, t):
+    """t = a + b v + c n (time per point and per message), least squares."""
+    v, n, t = (np.asarray(z, dtype=np.float64) for z in (v, n, t))
+    if len(t) < 4:
+        return None
+    A = np.stack([np.ones_like(v), v, n], axis=1)
+    coef, *_ = np.linalg.lstsq(A, t, rcond=None)
+    pred = A @ coef
+    ss_tot = float(np.sum((t - t.mean()) ** 2))
+    return {"intercept_ms": float(coef[0]), "ms_per_point": float(coef[1]), "ms_per_message": float(coef[2]),
+            "r2": 1 - float(np.sum((t - pred) ** 2)) / ss_tot if ss_tot > 0 else None,
+            "effective_exchange_GBs": (16.0 / (coef[1] * 1e-3) / 1e9) if coef[1] > 0 else None}
+
+
 def summary(v, t):
     v = np.asarray(v)
     t = np.asarray(t)
@@ -175,6 +189,7 @@ def transpose_parts(dims, P, perms, modes, reps, timer, x, y):
     for p, s in pairs:
         keys.setdefault(relabel(dims, p, s), []).append((p, s))
     X = {m: np.full((len(perms), len(perms)), np.nan) for m in modes}
+    parts = []
     t_start = time.perf_counter()
     for n, ((D, sig), members) in enumerate(sorted(keys.items())):
         order = complete_order(M, sig)
@@ -182,6 +197,19 @@ def transpose_parts(dims, P, perms, modes, reps, timer, x, y):
             plan = fftrw.Plan(D, P, order, flags=MODES[m])
             xv, yv = x.view(D), y.view(fftrw_layout(D, sig))
             ms = timer(lambda: plan.exec_transpose(0, xv, yv), reps)
+            if m == "staged":
+                # pack / exchange / unpack of this transpose (the plan's first),
+                # from the stage timings of whole forward transforms
+                plan.set_timing(True)
+                st = []
+                for _ in range(reps):
+                    plan.exec_fwd(x.view(D), y.view(D))
+                    st.append(plan.timings()[1:4])
+                st = np.median(np.array(st), axis=0)
+                vol = fftrw.fft_comm_volume(D, P, order)[0][0]
+                parts.append({"sizes": list(D), "to": list(sig), "volume": int(vol), "messages": plan.messages()[0],
+                              "transpose_ms": ms,
+                              "pack_ms": float(st[0]), "exchange_ms": float(st[1]), "unpack_ms": float(st[2])})
             plan.destroy()
             for p, s in members:
                 X[m][index[p], index[s]] = ms
@@ -199,7 +227,7 @@ def transpose_parts(dims, P, perms, modes, reps, timer, x, y):
         plan.destroy()
     for i, p in enumerate(perms):
         F[i] = by_len[dims[p[-1]]]
-    return X, F, len(keys), by_len
+    return X, F, len(keys), by_len, parts
 
 
 def fftrw_layout(dims, perm):
@@ -248,8 +276,18 @@ def study(dims, P, modes, reps, all_orders, compose, n_random, n_ties):
         out["per_order_volume"] = V.tolist()
     if compose:
         cm = [m for m in modes if m != "fused"]
-        X, F, nkeys, by_len = transpose_parts(dims, P, perms, cm, reps, timer, x, y)
+        X, F, nkeys, by_len, parts = transpose_parts(dims, P, perms, cm, reps, timer, x, y)
         out["composed"] = {"distinct_transposes": nkeys, "fft_step_ms_by_length": by_len}
+        if parts:
+            vol = [q["volume"] for q in parts]
+            out["staged_parts"] = {
+                "transposes": parts,
+                "exchange_fit": linear_fit(vol, [q["exchange_ms"] for q in parts]),
+                "exchange_fit_volume_messages": two_term_fit(vol, [q["messages"] for q in parts],
+                                                             [q["exchange_ms"] for q in parts]),
+                "pack_ms_median": float(np.median([q["pack_ms"] for q in parts])),
+                "unpack_ms_median": float(np.median([q["unpack_ms"] for q in parts])),
+                "transpose_fit": linear_fit(vol, [q["transpose_ms"] for q in parts])}
         comp = {}
         for m in cm:
             t = composed_times(seq, X[m], F)

@@ -87,6 +87,11 @@ def test_transpose_bit_exact_and_counted(gpu_lib, dims, P, order, dtype, staged)
         want = decomp.pair_volume(dims, P, a, b)
         assert analytic[t] == want
         assert moved[t] == want, (t, moved[t], want)
+        if staged and P <= 256:
+            # messages of the all-to-all: off-diagonal pairs that share points
+            C = decomp.pair_matrix(dims, P, a, b)
+            np.fill_diagonal(C, 0)
+            assert plan.messages()[t] == int(np.count_nonzero(C)), t
 
 
 @pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
