@@ -60,7 +60,7 @@ struct BatchCounters {
 };
 
 // task starts of one level held in LDS for the per-unit search
-constexpr int kLevelTasksLds = 1024;
+constexpr int kLevelTasksLds = 256;
 
 // real-time clock ticks (100 MHz) a work-group may wait at one barrier
 constexpr unsigned long long kWaitTicks = 200000000ull;
@@ -78,6 +78,8 @@ __global__ void __launch_bounds__(kThreads)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t s_unit0[kLevelTasksLds];
+    __shared__ int64_t s_unit;
+    __shared__ int s_task;
     for (int lv = 0; lv < nlevels; ++lv) {
         const int64_t nunits = level_units[lv];
         const int t0 = level_task0[lv], t1 = level_task0[lv + 1];
@@ -86,17 +88,34 @@ __global__ void __launch_bounds__(kThreads)
         if (in_lds)
             for (int i = threadIdx.x; i < t1 - t0; i += kThreads) s_unit0[i] = tasks[t0 + i].unit0;
         __syncthreads();
-        // units are dealt out round-robin: no shared claim counter
-        for (int64_t u = blockIdx.x; u < nunits; u += gridDim.x) {
-            int lo = 0, hi = t1 - t0 - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if ((in_lds ? s_unit0[mid] : tasks[t0 + mid].unit0) <= u)
-                    lo = mid;
-                else
-                    hi = mid - 1;
+        // thread 0 claims units from the level's counter -- the next claim is
+        // issued before the current unit runs, hiding its latency -- finds the
+        // unit's task and hands both to the work-group
+        unsigned long long next = 0;
+        if (threadIdx.x == 0) next = atomicAdd(&ctr->next[lv], 1ull);
+        for (;;) {
+            if (threadIdx.x == 0) {
+                const int64_t u = (int64_t)next;
+                int lo = 0;
+                if (u < nunits) {
+                    next = atomicAdd(&ctr->next[lv], 1ull);
+                    int hi = t1 - t0 - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if ((in_lds ? s_unit0[mid] : tasks[t0 + mid].unit0) <= u)
+                            lo = mid;
+                        else
+                            hi = mid - 1;
+                    }
+                }
+                s_unit = u;
+                s_task = t0 + lo;
             }
-            lo += t0;
+            __syncthreads();
+            const int64_t u = s_unit;
+            const int lo = s_task;
+            __syncthreads();  // every thread has read them before they change
+            if (u >= nunits) break;
             const BatchTask tk = tasks[lo];
             const BatchItemDev &it = items[tk.item];
             const int64_t local = u - tk.unit0;

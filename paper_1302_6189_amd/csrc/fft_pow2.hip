@@ -255,8 +255,6 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
     constexpr int LDS_FFT = NP > 1 ? RW * (N + N / 16) : 1;
     constexpr int LDS_STG = N * SROW;
     __shared__ C lds[LDS_FFT > LDS_STG ? LDS_FFT : LDS_STG];
-    __shared__ int own_a[RW];
-    __shared__ int own_b[N];
     __shared__ int moved_wg;
 
     const int64_t tiles_v = (d.Nv + RW - 1) / RW;
@@ -277,20 +275,36 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
             bbase += ci * d.bb[i];
         }
     }
+    // owner changes of this group's rows: row v keeps the k whose row index in
+    // B falls inside the range of v's owner (B's owner is monotone in k), an
+    // interval count; the rest move
+    int moved = 0;
     if (d.count) {
-        const bool narrow = d.owner32 != 0;
         if (threadIdx.x == 0) moved_wg = 0;
-        for (int r = threadIdx.x; r < nv; r += NT) {
+        if (threadIdx.x < nv) {
+            const bool narrow = d.owner32 != 0;
+            const int r = threadIdx.x;
             int64_t row = 0;
             for (int j = 0; j < d.ka; ++j) row += (d.srca[j] == 3 ? v0 + r : (int64_t)bc[d.srca[j]]) * d.wa[j];
             int64_t o = fx_owner(row, d.P, d.Ra, narrow);
             if (d.mu) o = d.mu[o];
-            own_a[r] = (int)o;
-        }
-        for (int k = threadIdx.x; k < N; k += NT) {
-            int64_t row = 0;
-            for (int j = 0; j < d.kb; ++j) row += (d.srcb[j] == 4 ? (int64_t)k : (int64_t)bc[d.srcb[j]]) * d.wb[j];
-            own_b[k] = (int)fx_owner(row, d.P, d.Rb, narrow);
+            int64_t rb0 = 0, wk = 0;
+            for (int j = 0; j < d.kb; ++j) {
+                if (d.srcb[j] == 4)
+                    wk = d.wb[j];
+                else
+                    rb0 += (int64_t)bc[d.srcb[j]] * d.wb[j];
+            }
+            int64_t keep;
+            if (wk == 0) {
+                keep = fx_owner(rb0, d.P, d.Rb, narrow) == o ? N : 0;
+            } else {
+                const int64_t lo = (d.Rb * o) / d.P - rb0, hi = (d.Rb * (o + 1)) / d.P - rb0;
+                auto cdiv = [&](int64_t x) { return x >= 0 ? (x + wk - 1) / wk : x / wk; };
+                const int64_t k0 = max<int64_t>(0, cdiv(lo)), k1 = min<int64_t>(N, cdiv(hi));
+                keep = max<int64_t>(0, k1 - k0);
+            }
+            moved = (int)(N - keep);
         }
     }
 
@@ -330,7 +344,6 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
     }
     __syncthreads();
     // runs of consecutive v for every k, two values per 16-byte store
-    int moved = 0;
     constexpr int HP = RW / 2;
     const int npair = (nv + 1) / 2;
     C *dstb = out + bbase + v0;
@@ -351,10 +364,8 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
                 st_nt(p, a0);
                 st_nt(p + 1, a1);
             }
-            if (d.count) moved += (own_a[r0] != own_b[k]) + (own_a[r0 + 1] != own_b[k]);
         } else {
             st_nt(p, a0);
-            if (d.count) moved += own_a[r0] != own_b[k];
         }
     }
     if (d.count) {

@@ -13,10 +13,11 @@
 // Owner counting: virtual process p owns a contiguous range of rows over the
 // first k axes of its decomposition (Eqs. (13)-(15)).  The first k axes of A
 // never include u and those of B never include v (k < M), so inside a tile
-// A's owner depends only on (slice, v) and B's only on (slice, u).  Each tile
-// computes the two owner vectors once, then counts the (u, v) pairs whose
-// owners differ: the points this tile moves between processes.  Summed over
-// tiles this is the paper's communication amount for the transpose.
+// A's owner depends only on (slice, v) and B's only on (slice, u), and B's
+// row index grows linearly with u.  For each (slice, v) the points that keep
+// their owner are the u whose B row falls in that owner's range, an interval;
+// the rest of the row moves.  Summed over tiles this is the paper's
+// communication amount for the transpose.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -109,11 +110,54 @@ __device__ __forceinline__ void tile_owners(const XposeDesc &d, int64_t g0, int 
     }
 }
 
-// LDS bytes of a tile (and the owner vectors when counting), 16-byte aligned
+// Points of one tile whose owner changes, this thread's share: for each
+// (slice, v) row, A's owner o is fixed and B's owner is monotone in u, so the
+// u that stay with o are those whose row index in B lies in o's range -- an
+// interval count, no per-point comparison.
+__device__ __forceinline__ int tile_moved(const XposeDesc &d, int64_t g0, int ng, int64_t u0, int nu, int64_t v0,
+                                          int nv)
+{
+    const bool narrow = d.owner32 != 0;
+    int moved = 0;
+    for (int i = threadIdx.x; i < ng * nv; i += kThreads) {
+        const int g = i / nv, iv = i - g * nv;
+        int c[3];
+        int64_t ab, bb;
+        slice_coords(d, g0 + g, c, &ab, &bb);
+        int64_t r = 0;
+        for (int j = 0; j < d.ka; ++j) {
+            const int src = d.srca[j];
+            r += (src == 3 ? v0 + iv : (int64_t)c[src]) * d.wa[j];
+        }
+        int64_t o = owner_of_row(r, d.P, d.Ra, narrow);
+        if (d.mu) o = d.mu[o];
+        int64_t rb0 = 0, wu = 0;
+        for (int j = 0; j < d.kb; ++j) {
+            const int src = d.srcb[j];
+            if (src == 4)
+                wu = d.wb[j];
+            else
+                rb0 += (int64_t)c[src] * d.wb[j];
+        }
+        int64_t keep;
+        if (wu == 0) {
+            keep = owner_of_row(rb0, d.P, d.Rb, narrow) == o ? nu : 0;
+        } else {
+            // u in [u0, u0 + nu) with row_lo(o) <= rb0 + u wu < row_lo(o + 1)
+            const int64_t lo = (d.Rb * o) / d.P - rb0, hi = (d.Rb * (o + 1)) / d.P - rb0;
+            auto cdiv = [&](int64_t x) { return x >= 0 ? (x + wu - 1) / wu : x / wu; };
+            const int64_t k0 = max<int64_t>(u0, cdiv(lo)), k1 = min<int64_t>(u0 + nu, cdiv(hi));
+            keep = max<int64_t>(0, k1 - k0);
+        }
+        moved += nu - (int)keep;
+    }
+    return moved;
+}
+
+// LDS bytes of a tile, 16-byte aligned
 __host__ __device__ inline size_t xpose_tile_bytes(const XposeDesc &d, size_t esz)
 {
     size_t b = (size_t)d.G * d.TV * (d.TU + 1) * esz;
-    if (d.count) b += (size_t)d.G * (d.TU + d.TV) * sizeof(int);
     return (b + 15) & ~(size_t)15;
 }
 
@@ -138,11 +182,10 @@ __device__ __forceinline__ void xpose_tile(const C *__restrict__ in, C *__restri
     const int nv = (int)min<int64_t>(TV, d.Nv - v0);
     const int ng = (int)min<int64_t>(d.G, d.nslices - g0);
 
-    int *own_a = reinterpret_cast<int *>(tile + (size_t)d.G * TV * ldt);
-    int *own_b = own_a + d.G * TV;
+    int moved = 0;
     if (d.count) {
         if (threadIdx.x == 0) moved_wg = 0;
-        tile_owners(d, g0, ng, u0, nu, v0, nv, own_a, own_b);
+        moved = tile_moved(d, g0, ng, u0, nu, v0, nv);
     }
 
     // load: rows (g, v) of contiguous u-values
@@ -180,7 +223,6 @@ __device__ __forceinline__ void xpose_tile(const C *__restrict__ in, C *__restri
     __syncthreads();
 
     // store: rows (g, u) of contiguous v-values
-    int moved = 0;
     {
         const int per_row = TV / VV;
         const int tx = threadIdx.x % per_row;
@@ -208,11 +250,6 @@ __device__ __forceinline__ void xpose_tile(const C *__restrict__ in, C *__restri
                     __builtin_nontemporal_store(w, reinterpret_cast<xf4 *>(p));
                 } else {
                     xst(p, tcol[0]);
-                }
-                if (d.count) {
-                    const int ob = own_b[g * TU + iu];
-                    moved += own_a[g * TV + iv] != ob;
-                    if (VV == 2) moved += own_a[g * TV + iv + 1] != ob;
                 }
             }
         }

@@ -275,3 +275,24 @@ def test_fused_leave_permuted_and_in_place(gpu_lib):
     xd = to_dev(x)
     plan2.exec_fwd(xd, xd)
     assert dft.rel_l2(to_host(xd), ref) < 1e-5
+
+
+@pytest.mark.parametrize("fused", [False, True])
+@pytest.mark.parametrize("dims,P,oidx", [((16, 16, 16), 48, 3), ((32, 32, 32), 100, 5), ((32, 16, 64), 7, 1),
+                                         ((8, 8, 16, 16), 20, 700), ((16, 16, 16, 16), 300, 1295)])
+def test_matched_ownership_device_counts(gpu_lib, dims, P, oidx, fused):
+    # the relabelled ranges of the matched reading, counted on the device
+    M = len(dims)
+    order = fftrw.fft_order_at(M, oidx)
+    flags = fftrw.FLAG_COUNT_MOVED | fftrw.FLAG_OWN_MATCHED | (fftrw.FLAG_FUSED_FFT if fused else 0)
+    plan = fftrw.Plan(dims, P, order, flags=flags)
+    x = inputs.uniform(dims, 17, np.complex64)
+    xd = to_dev(x)
+    yd = empty_dev(dims, np.complex64)
+    plan.exec_fwd(xd, yd)
+    analytic, moved = plan.stats()
+    steps, ret = decomp.order_volumes(dims, P, order, ownership="matched")
+    assert analytic == steps + [ret]
+    assert moved == analytic
+    ref = dft.fftn_direct(x, orders.fft_axis_sequence(order))
+    assert dft.rel_l2(to_host(yd), ref) < 1e-5
