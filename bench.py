@@ -263,7 +263,14 @@ def main():
         torch.cuda.synchronize()
         z.copy_(x)
         torch.cuda.synchronize()
-        print(json.dumps({"pmc_probe": "done", "bytes_per_copy": 2 * T * 8}), flush=True)
+        # the staged path of the same order: pack, exchange and unpack per transpose
+        sp = fftrw.Plan(dims, P, order, dtype=fftrw.C64, flags=fftrw.FLAG_STAGED)
+        sp.exec_fwd(x, y, stream)
+        torch.cuda.synchronize()
+        steps, _, ret = fftrw.fft_comm_volume(dims, P, order)
+        sp.destroy()
+        print(json.dumps({"pmc_probe": "done", "bytes_per_copy": 2 * T * 8, "staged_moved": steps + [ret]}),
+              flush=True)
         return
 
     for _ in range(args.warmup):
