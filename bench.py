@@ -54,24 +54,50 @@ def measured_traffic(kernel: str):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(dims, x_host):
     """The FP64 oracle, as it stands, on a bounded sample: every axis's 1-D FFT
-    pass over a quarter of the array (whole rows), scaled to one transform."""
+    pass over a quarter of the array (whole rows), scaled to one transform; then
+    the same on one thread over a sixteenth of the array."""
     import numpy as np
 
     from oracle import dft
-    S = dims[0] // 4
-    t0 = time.perf_counter()
-    dft.fft_along_axis(x_host[0:S].astype(np.complex128), 2)
-    dft.fft_along_axis(x_host[0:S].astype(np.complex128), 1)
-    dft.fft_along_axis(x_host[:, 0:S].astype(np.complex128), 0)
-    sec = time.perf_counter() - t0
     T = math.prod(dims)
+
+    def passes(S):
+        t0 = time.perf_counter()
+        dft.fft_along_axis(x_host[0:S].astype(np.complex128), 2)
+        dft.fft_along_axis(x_host[0:S].astype(np.complex128), 1)
+        dft.fft_along_axis(x_host[:, 0:S].astype(np.complex128), 0)
+        return time.perf_counter() - t0
+
+    threads = dft.num_threads()
+    S = dims[0] // 4
+    sec = passes(S)
     full = sec * dims[0] / S
+    dft.set_threads(1)
+    S1 = dims[0] // 16
+    sec1 = passes(S1)
+    dft.set_threads(threads)
+    full1 = sec1 * dims[0] / S1
     return {"value": round(5 * T * math.log2(T) / full / 1e9, 3), "unit": "GFLOP/s",
-            "cores": dft.num_threads(), "kind": "oracle",
+            "cores": threads, "kind": "oracle",
             "sample": f"FP64 recursive-FFT oracle, each axis's pass over 1/4 of the 512^3 array "
-                      f"({sec:.2f} s measured, x{dims[0] // S} to one transform)"}
+                      f"({sec:.2f} s measured, x{dims[0] // S} to one transform)",
+            "one_thread": {"value": round(5 * T * math.log2(T) / full1 / 1e9, 3), "unit": "GFLOP/s",
+                           "sample": f"each axis's pass over 1/16 of the array on one thread ({sec1:.2f} s, "
+                                     f"x{dims[0] // S1})"},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
 def time_fwd(plan, x, y, stream, reps, warm=3):

@@ -112,6 +112,17 @@ int oracle_fft_rows(double *data, int64_t nrows, int64_t n, int sign)
     return failed ? -1 : 0;
 }
 
+/* Threads for later OpenMP regions (no effect without OpenMP). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Number of threads an OpenMP region would use (1 without OpenMP). */
 int oracle_num_threads(void)
 {

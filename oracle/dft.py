@@ -39,6 +39,8 @@ def _load():
         lib.oracle_fft_rows.argtypes = [ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_int64, ctypes.c_int]
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.restype = None
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -46,6 +48,11 @@ def _load():
 def num_threads() -> int:
     """Threads the C oracle's OpenMP regions use."""
     return int(_load().oracle_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads for the C oracle's later OpenMP regions."""
+    _load().oracle_set_threads(int(n))
 
 
 # ----------------------------------------------------------------------------
