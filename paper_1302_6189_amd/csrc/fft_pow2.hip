@@ -275,7 +275,28 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
             bbase += ci * d.bb[i];
         }
     }
-    // owner changes of this group's rows: row v keeps the k whose row index in
+    const int lane = threadIdx.x % L;
+    const int r = threadIdx.x / L;
+    const bool active = r < nv;
+    const C *src = in + abase + (v0 + r) * d.a_sv;
+    C v[E];
+    {
+        using PI = PassInfo<N, RL, 0>;
+        constexpr int R = PI::R, B = E / R;
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                C t[B];
+                load_run<B>(src + lane * B + i * PI::NB, t);
+#pragma unroll
+                for (int b = 0; b < B; ++b) v[b * R + i] = t[b];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = mk<C>(0, 0);
+        }
+    }
+    // (computed while the row loads are in flight) owner changes of this group's rows: row v keeps the k whose row index in
     // B falls inside the range of v's owner (B's owner is monotone in k), an
     // interval count; the rest move
     int moved = 0;
@@ -308,27 +329,6 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
         }
     }
 
-    const int lane = threadIdx.x % L;
-    const int r = threadIdx.x / L;
-    const bool active = r < nv;
-    const C *src = in + abase + (v0 + r) * d.a_sv;
-    C v[E];
-    {
-        using PI = PassInfo<N, RL, 0>;
-        constexpr int R = PI::R, B = E / R;
-        if (active) {
-#pragma unroll
-            for (int i = 0; i < R; ++i) {
-                C t[B];
-                load_run<B>(src + lane * B + i * PI::NB, t);
-#pragma unroll
-                for (int b = 0; b < B; ++b) v[b * R + i] = t[b];
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = mk<C>(0, 0);
-        }
-    }
     run_passes<N, E, DIR, RL, 0>(v, lds + r * (N + N / 16), lane, tw);
     {   // last pass outputs (row r, k = j + i N/R) into the staging block
         using PI = PassInfo<N, RL, NP - 1>;
@@ -369,11 +369,20 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
         }
     }
     if (d.count) {
-        for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
-        if ((threadIdx.x & 63) == 0 && moved) atomicAdd(&moved_wg, moved);
-        __syncthreads();
-        if (threadIdx.x == 0 && moved_wg)
-            atomicAdd(d.counter + (blockIdx.x % kCountSlots) * kCountStride, (unsigned long long)moved_wg);
+        if constexpr (RW <= 64) {
+            // only rows < nv <= 64 counted: wave 0 holds every term
+            if (threadIdx.x < 64) {
+                for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
+                if (threadIdx.x == 0 && moved)
+                    atomicAdd(d.counter + (blockIdx.x % kCountSlots) * kCountStride, (unsigned long long)moved);
+            }
+        } else {
+            for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
+            if ((threadIdx.x & 63) == 0 && moved) atomicAdd(&moved_wg, moved);
+            __syncthreads();
+            if (threadIdx.x == 0 && moved_wg)
+                atomicAdd(d.counter + (blockIdx.x % kCountSlots) * kCountStride, (unsigned long long)moved_wg);
+        }
     }
 }
 
