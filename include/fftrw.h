@@ -78,8 +78,10 @@ enum {
     FFTRW_FLAG_OWN_MATCHED = 8u,     /* ownership reading R2 (see fft_comm_volume)*/
     FFTRW_FLAG_FUSED_FFT = 16u,      /* fuse each FFT step with the transpose that
                                         follows it (one HBM pass per step)        */
-    FFTRW_FLAG_BATCH_NO_GRAPH = 32u  /* batched form: launch the persistent kernel
+    FFTRW_FLAG_BATCH_NO_GRAPH = 32u, /* batched form: launch the persistent kernel
                                         directly instead of replaying a graph     */
+    FFTRW_FLAG_BATCH_NO_FUSE = 64u   /* batched form: separate FFT and transpose
+                                        stages (allows in == out)                 */
 };
 
 typedef struct fft_plan_s *fft_plan_t;
@@ -283,21 +285,26 @@ typedef struct fft_batch_s *fft_batch_t;
 /*
  * fft_batch_plan -- plan n independent transforms (each the Fig. 4 pipeline)
  * to run together in ONE persistent kernel launch, replayed from a HIP graph.
- * The work of every item is cut into units (row blocks of an FFT step, tiles
- * of a transpose), numbered stage level by stage level; work-groups take
- * units from an atomic counter and wait, per item, for the item's earlier
- * stages (bounded waits: a wait past its limit sets the error flag reported by
- * fft_batch_stats and the unit is skipped).  precision must be
- * FFTRW_PREC_NATIVE; flags: COUNT_MOVED, LEAVE_PERMUTED, BATCH_NO_GRAPH.
- * tune_cache: path of the autotuner's cache (fft_autotune) or NULL for the
- * built-in plan.  Each item's row lengths follow fft_plan's rules; the batch
- * owns one T_i-element workspace per item.
+ * The work of every item is cut into units, numbered stage level by stage
+ * level (level s holds stage s of every item).  By default stage t of an item
+ * is its FFT step t fused with the transpose that follows (a unit: a block of
+ * rows consecutive in the next layout's last axis); with BATCH_NO_FUSE the
+ * FFT steps (row blocks) and transposes (tiles) are stages of their own.
+ * Work-groups claim units from a per-level atomic counter and meet at a grid
+ * barrier between levels; a wait past its time limit sets the error flag
+ * reported by fft_batch_stats.  precision must be FFTRW_PREC_NATIVE; flags:
+ * COUNT_MOVED, LEAVE_PERMUTED, BATCH_NO_GRAPH, BATCH_NO_FUSE.  tune_cache:
+ * path of the autotuner's cache (fft_autotune) or NULL for the built-in plan.
+ * Each item's row lengths follow fft_plan's rules; the batch owns one
+ * T_i-element workspace per item.
  */
 int fft_batch_plan(fft_batch_t *batch, int n, const fft_item_desc *items,
                    int precision, const char *tune_cache, unsigned flags);
 
 /* Forward / inverse of every item: in[i], out[i] are device pointers to T_i
- * complex64 values in natural layout (host arrays of n pointers).  One graph
+ * complex64 values in natural layout (host arrays of n pointers); in[i] must
+ * differ from out[i] unless the batch was planned with BATCH_NO_FUSE
+ * (FFTRW_E_ARG otherwise).  One graph
  * launch on `stream` (the first call per direction captures it). */
 int fft_batch_exec_fwd(fft_batch_t batch, void *const *in, void *const *out,
                        void *stream);

@@ -23,6 +23,7 @@
 #include "decomp.hpp"
 #include "errors.hpp"
 #include "fft_generic.hpp"
+#include "fused_generic.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
 #include "tune.hpp"
@@ -37,7 +38,11 @@ struct BatchItemDev {
     float2 *out;
     float2 *work;
     int M;
-    int nstage;                     // 2M, or 2M - 1 with LEAVE_PERMUTED
+    int nstage;                     // 2M (2M - 1 with LEAVE_PERMUTED); fused: M
+    int fused;                      // stage t = FFT step t fused with transpose t
+    int nx;                         // transposes executed (M, or M - 1 with LEAVE_PERMUTED)
+    int frw[kMaxDims];              // rows (consecutive v) per slice of a fused unit of stage t
+    int fg[kMaxDims];               // slices per fused unit of stage t
     int src[kMaxStages];            // 0 in, 1 out, 2 work
     int dst[kMaxStages];
     int64_t prefix[kMaxStages + 1]; // units of this item before stage s
@@ -122,6 +127,17 @@ __global__ void __launch_bounds__(kThreads)
             const int st = tk.stage;
             const float2 *src = batch_buf(it, it.src[st]);
             float2 *dst = batch_buf(it, it.dst[st]);
+            if (it.fused) {
+                const bool last = st == it.M - 1;
+                const float sc = DIR > 0 && last ? it.inv_scale : 1.f;
+                if (st < it.nx)
+                    fft_xpose_unit<float2, DIR>(src, dst, it.fft[st], it.xp[st], it.frw[st], it.fg[st], local,
+                                                sc, DIR > 0 && last, smem);
+                else
+                    fft_rows_block<float2, DIR>(src, dst, it.fft[st], local, sc, DIR > 0 && last,
+                                                reinterpret_cast<float2 *>(smem));
+                continue;
+            }
             const int t = st >> 1;
             if ((st & 1) == 0) {
                 const bool last = t == it.M - 1;
@@ -195,6 +211,7 @@ struct fft_batch_impl {
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     bool pointers_set = false;
     bool tuned = false;  // a matching autotuner cache was applied
+    bool any_fused = false;
 };
 
 namespace {
@@ -258,8 +275,10 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
     *out = nullptr;
     if (precision != FFTRW_PREC_NATIVE)
         return fail(FFTRW_E_UNSUPPORTED, "the batched form runs the FP32 Stockham kernels");
-    if (flags & ~(unsigned)(FFTRW_FLAG_COUNT_MOVED | FFTRW_FLAG_LEAVE_PERMUTED | FFTRW_FLAG_BATCH_NO_GRAPH))
-        return fail(FFTRW_E_UNSUPPORTED, "the batched form supports COUNT_MOVED, LEAVE_PERMUTED and NO_GRAPH only");
+    if (flags & ~(unsigned)(FFTRW_FLAG_COUNT_MOVED | FFTRW_FLAG_LEAVE_PERMUTED | FFTRW_FLAG_BATCH_NO_GRAPH |
+                            FFTRW_FLAG_BATCH_NO_FUSE))
+        return fail(FFTRW_E_UNSUPPORTED,
+                    "the batched form supports COUNT_MOVED, LEAVE_PERMUTED, BATCH_NO_GRAPH and BATCH_NO_FUSE only");
     fft_batch_s *b = new (std::nothrow) fft_batch_s();
     if (!b) return fail(FFTRW_E_NOMEM, "out of host memory");
     b->n = n;
@@ -284,13 +303,53 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
         std::memset(&d, 0, sizeof(d));
         d.M = it.M;
         const int nx = leave ? it.M - 1 : it.M;
-        d.nstage = it.M + nx;
+        d.nx = nx;
         d.work = (float2 *)p->work;
         d.inv_scale = (float)(1.0 / (double)p->T);
+        int64_t units = 0;
+        // fused schedule: one unit = RW rows consecutive in v of one slice, the
+        // largest power of two with RW (N + 1) <= 4096 that the v axis can fill
+        d.fused = !(flags & FFTRW_FLAG_BATCH_NO_FUSE);
+        if (d.fused) {
+            d.nstage = it.M;
+            int cur = 0;
+            for (int t = 0; t < it.M; ++t) {
+                d.prefix[t] = units;
+                d.fft[t] = p->fft[t];
+                if (t < nx) {
+                    d.xp[t] = p->xp[t];
+                    const int N = d.fft[t].N;
+                    // rows per slice: up to the v extent; then slices until the
+                    // unit holds about 4096 values (and each row >= one lane)
+                    int rw = 1;
+                    while (rw * 2 <= 256 && (int64_t)rw * 2 * (N + 1) <= 4096 && rw * 2 <= 2 * d.xp[t].Nv - 1) rw *= 2;
+                    int G = 1;
+                    while (G * 2 * rw <= 256 && (int64_t)G * 2 * rw * (N + 1) <= 4096 && G * 2 <= 2 * d.xp[t].nslices - 1)
+                        G *= 2;
+                    d.frw[t] = rw;
+                    d.fg[t] = G;
+                    d.src[t] = t == 0 ? 0 : cur;
+                    d.dst[t] = ((nx - 1 - t) % 2 == 0) ? 1 : 2;
+                    cur = d.dst[t];
+                    units += ((d.xp[t].Nv + rw - 1) / rw) * ((d.xp[t].nslices + G - 1) / G);
+                    lds = std::max(lds, fused_unit_bytes(N, rw, G, 8));
+                } else {
+                    // LEAVE_PERMUTED: the last FFT step runs in place on the output
+                    d.src[t] = 1;
+                    d.dst[t] = 1;
+                    units += (d.fft[t].nrows + d.fft[t].rows_per_wg - 1) / d.fft[t].rows_per_wg;
+                    lds = std::max(lds, (size_t)d.fft[t].rows_per_wg * d.fft[t].N * 8);
+                }
+            }
+            d.prefix[d.nstage] = units;
+            max_stage = std::max(max_stage, d.nstage);
+            b->any_fused = true;
+            continue;
+        }
+        d.nstage = it.M + nx;
         // buffer sequence of the pipeline: FFT 0 reads the input; transposes alternate
         const int b0 = (nx % 2 == 0) ? 1 : 2, b1 = b0 == 1 ? 2 : 1;
         int cur = b0, other = b1;
-        int64_t units = 0;
         for (int st = 0; st < d.nstage; ++st) {
             d.prefix[st] = units;
             const int t = st >> 1;
@@ -386,6 +445,9 @@ static int batch_exec(fft_batch_t b, void *const *in, void *const *out, void *st
     bool changed = !b->pointers_set;
     for (int i = 0; i < b->n; ++i) {
         if (!in[i] || !out[i]) return fail(FFTRW_E_ARG, "null buffer for item " + std::to_string(i));
+        if (b->h_items[i].fused && in[i] == out[i])
+            return fail(FFTRW_E_ARG, "item " + std::to_string(i) +
+                                         ": fused stages need in != out (plan with FFTRW_FLAG_BATCH_NO_FUSE for in place)");
         BatchItemDev &d = b->h_items[i];
         if (d.in != in[i] || d.out != out[i]) changed = true;
         d.in = (const float2 *)in[i];

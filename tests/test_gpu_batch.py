@@ -128,3 +128,39 @@ def test_autotuned_batch(gpu_lib, tmp_path):
     ins3, outs3 = _run(plain, xs)
     for i in range(len(items)):
         assert np.array_equal(to_host(outs2[i]), to_host(outs3[i]))
+
+
+@pytest.mark.parametrize("leave", [False, True])
+def test_fused_schedule_matches_separate_stages(gpu_lib, leave):
+    # FFT steps fused with their transposes run the same passes on the same data
+    items = inputs.batch_items(24, seed=5)
+    xs = [inputs.uniform(d, 500 + i, np.complex64) for i, (d, _) in enumerate(items)]
+    extra = fftrw.FLAG_LEAVE_PERMUTED if leave else 0
+    fused = fftrw.Batch(items, flags=fftrw.FLAG_COUNT_MOVED | extra)
+    plain = fftrw.Batch(items, flags=fftrw.FLAG_COUNT_MOVED | fftrw.FLAG_BATCH_NO_FUSE | extra)
+    for fwd in (True, False):
+        _, a = _run(fused, xs, fwd)
+        _, b = _run(plain, xs, fwd)
+        for i in range(len(items)):
+            assert np.array_equal(to_host(a[i]), to_host(b[i])), (i, fwd)
+    sa, sb = fused.stats(), plain.stats()
+    assert sa["error"] == 0 and sb["error"] == 0
+    assert sa["moved"] == sb["moved"]
+    for mi, ai in zip(sa["moved"], sa["analytic"]):
+        assert all(m == -1 or m == a_ for m, a_ in zip(mi, ai))
+        assert (mi[-1] == -1) == leave
+
+
+def test_in_place_needs_the_separate_schedule(gpu_lib):
+    items = [((12, 16, 20), 5), ((16, 16, 16, 16), 30)]
+    xs = [inputs.uniform(d, 70 + i, np.complex64) for i, (d, _) in enumerate(items)]
+    ins = [to_dev(x) for x in xs]
+    with pytest.raises(fftrw.FftrwError) as e:
+        fftrw.Batch(items).exec_fwd(ins, ins)
+    assert e.value.code == fftrw.E_ARG
+    b = fftrw.Batch(items, flags=fftrw.FLAG_BATCH_NO_FUSE)
+    b.exec_fwd(ins, ins)
+    for i, (d, P) in enumerate(items):
+        order = fftrw.fft_order_search(d, P)["best_order"]
+        ref = dft.fftn_direct(xs[i], orders.fft_axis_sequence(order))
+        assert dft.rel_l2(to_host(ins[i]), ref) < 1e-5
