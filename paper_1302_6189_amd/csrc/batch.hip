@@ -319,13 +319,8 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
                 if (t < nx) {
                     d.xp[t] = p->xp[t];
                     const int N = d.fft[t].N;
-                    // rows per slice: up to the v extent; then slices until the
-                    // unit holds about 4096 values (and each row >= one lane)
-                    int rw = 1;
-                    while (rw * 2 <= 256 && (int64_t)rw * 2 * (N + 1) <= 4096 && rw * 2 <= 2 * d.xp[t].Nv - 1) rw *= 2;
-                    int G = 1;
-                    while (G * 2 * rw <= 256 && (int64_t)G * 2 * rw * (N + 1) <= 4096 && G * 2 <= 2 * d.xp[t].nslices - 1)
-                        G *= 2;
+                    int rw = 1, G = 1;
+                    fused_unit_shape(N, d.xp[t].Nv, d.xp[t].nslices, 4096, &rw, &G);
                     d.frw[t] = rw;
                     d.fg[t] = G;
                     d.src[t] = t == 0 ? 0 : cur;

@@ -30,6 +30,8 @@ hipError_t pow2_make_twiddles(int N, bool fp64, void *tw, hipStream_t s);
 hipError_t launch_fft_pow2(int N, bool fp64, const void *tw, int64_t nrows, int dir, const void *in, void *out,
                            double scale, hipStream_t s);
 int pow2_rows_per_wg(int N, bool fp64);
+hipError_t launch_fft_xpose_generic(const FftDesc &f, const XposeDesc &d, bool fp64, int dir, const void *in,
+                                    void *out, double scale, hipStream_t s);
 hipError_t launch_fft_xpose_pow2(int N, bool fp64, const void *tw, const XposeDesc &fx, int dir, const void *in,
                                  void *out, double scale, hipStream_t s);
 hipError_t launch_fft256_mfma(int precision, int dir, const void *tw256, int64_t nrows, const void *in, void *out,
@@ -304,8 +306,12 @@ int run_pipeline(fft_plan_impl *pl, const void *in, void *out, hipStream_t s, in
             void *dst = ((nx - 1 - t) % 2 == 0) ? out : pl->work;
             const double scale = (dir > 0 && t == M - 1) ? 1.0 / (double)pl->T : 1.0;
             const FftDesc &d = pl->fft[t];
-            HIP_TRY(launch_fft_xpose_pow2(d.N, pl->esz == 16, d.tw, pl->xp[t], dir, src, dst, scale, s),
-                    "fused fft+transpose launch");
+            if (pl->fuse_kind[t] == 1)
+                HIP_TRY(launch_fft_xpose_pow2(d.N, pl->esz == 16, d.tw, pl->xp[t], dir, src, dst, scale, s),
+                        "fused fft+transpose launch");
+            else
+                HIP_TRY(launch_fft_xpose_generic(d, pl->xp[t], pl->esz == 16, dir, src, dst, scale, s),
+                        "fused fft+transpose launch");
             if (int rc = mark()) return rc;
             src = dst;
         }
@@ -496,17 +502,21 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
             }
         }
     }
-    // fusion of every FFT step with its transpose: power-of-two rows short enough
-    // that a work-group's run of consecutive v-values is at least 8 long
+    // fusion of every FFT step with its transpose: power-of-two rows of 16..512
+    // (256 in FP64) whose work-group's run of consecutive v-values fits the v
+    // axis use the compile-time kernel; 2,3,5-smooth rows use the generic unit
     if ((flags & FFTRW_FLAG_FUSED_FFT) && !(flags & FFTRW_FLAG_STAGED) && precision == FFTRW_PREC_NATIVE &&
         !generic_rows) {
         const bool fp64 = pl->esz == 16;
         const int nx = (flags & FFTRW_FLAG_LEAVE_PERMUTED) ? M - 1 : M;
         bool ok = true;
-        for (int t = 0; t < M && ok; ++t) {
+        for (int t = 0; t < nx && ok; ++t) {
             const FftDesc &d = pl->fft[t];
-            ok = d.pow2 && !d.mfma && d.N >= 16 && d.N <= (fp64 ? 256 : 512);
-            if (ok && t < nx) ok = pow2_rows_per_wg(d.N, fp64) <= pl->xp[t].Nv;
+            const bool pow2_ok = d.pow2 && !d.mfma && d.N >= 16 && d.N <= (fp64 ? 256 : 512) &&
+                                 pow2_rows_per_wg(d.N, fp64) <= pl->xp[t].Nv;
+            const bool generic_ok = !d.pow2 && !d.mfma && d.N + 1 <= (fp64 ? 2048 : 4096);
+            pl->fuse_kind[t] = pow2_ok ? 1 : (generic_ok ? 2 : 0);
+            ok = pl->fuse_kind[t] != 0;
         }
         pl->fused = ok;
     }

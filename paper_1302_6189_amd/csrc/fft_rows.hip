@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fft_generic.hpp"
+#include "fused_generic.hpp"
 
 namespace fftrw {
 
@@ -59,6 +60,45 @@ hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in,
         else
             hipLaunchKernelGGL((fft_rows_kernel<float2, 1>), grid, block, lds, s, (const float2 *)in,
                                (float2 *)out, d, (float)scale, do_scale);
+    }
+    return hipGetLastError();
+}
+
+template <typename C, int DIR>
+__global__ void __launch_bounds__(kThreads)
+    fft_xpose_generic_kernel(const C *in, C *out, FftDesc f, XposeDesc d, int rw, int G,
+                             typename RealOf<C>::type scale, int do_scale)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    fft_xpose_unit<C, DIR>(in, out, f, d, rw, G, blockIdx.x, scale, do_scale != 0, smem_raw);
+}
+
+// one FFT step of 2,3,5-smooth rows fused with the transpose that follows
+hipError_t launch_fft_xpose_generic(const FftDesc &f, const XposeDesc &d, bool fp64, int dir, const void *in,
+                                    void *out, double scale, hipStream_t s)
+{
+    int rw = 1, G = 1;
+    fused_unit_shape(f.N, d.Nv, d.nslices, fp64 ? 2048 : 4096, &rw, &G);
+    const int64_t nblk = ((d.Nv + rw - 1) / rw) * ((d.nslices + G - 1) / G);
+    if (nblk <= 0) return hipSuccess;
+    if (nblk >= (int64_t)0x7fffffff) return hipErrorInvalidValue;
+    const size_t lds = fused_unit_bytes(f.N, rw, G, fp64 ? 16 : 8);
+    const int do_scale = scale != 1.0;
+    dim3 grid((unsigned)nblk), block(kThreads);
+    if (fp64) {
+        if (dir < 0)
+            hipLaunchKernelGGL((fft_xpose_generic_kernel<double2, -1>), grid, block, lds, s, (const double2 *)in,
+                               (double2 *)out, f, d, rw, G, scale, do_scale);
+        else
+            hipLaunchKernelGGL((fft_xpose_generic_kernel<double2, 1>), grid, block, lds, s, (const double2 *)in,
+                               (double2 *)out, f, d, rw, G, scale, do_scale);
+    } else {
+        if (dir < 0)
+            hipLaunchKernelGGL((fft_xpose_generic_kernel<float2, -1>), grid, block, lds, s, (const float2 *)in,
+                               (float2 *)out, f, d, rw, G, (float)scale, do_scale);
+        else
+            hipLaunchKernelGGL((fft_xpose_generic_kernel<float2, 1>), grid, block, lds, s, (const float2 *)in,
+                               (float2 *)out, f, d, rw, G, (float)scale, do_scale);
     }
     return hipGetLastError();
 }

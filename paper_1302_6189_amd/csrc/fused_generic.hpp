@@ -22,6 +22,20 @@
 
 namespace fftrw {
 
+// Shape of a fused unit for rows of length N: RW rows per slice (a power of
+// two covering the v extent when it can) and G slices, so that a unit holds at
+// most `budget` values (4096 complex64, 2048 complex128) and every row keeps at
+// least one lane of the 256-thread group.
+inline void fused_unit_shape(int N, int64_t Nv, int64_t nslices, int budget, int *rw, int *G)
+{
+    int r = 1;
+    while (r * 2 <= 256 && (int64_t)r * 2 * (N + 1) <= budget && r * 2 <= 2 * Nv - 1) r *= 2;
+    int g = 1;
+    while (g * 2 * r <= 256 && (int64_t)g * 2 * r * (N + 1) <= budget && g * 2 <= 2 * nslices - 1) g *= 2;
+    *rw = r;
+    *G = g;
+}
+
 // LDS bytes of a fused unit: G * RW padded rows, the slices' bases, one int
 __host__ __device__ inline size_t fused_unit_bytes(int N, int rw, int G, size_t esz)
 {

@@ -64,6 +64,7 @@ struct fft_plan_impl {
     size_t dev_bytes = 0;
     bool executed = false;
     bool fused = false;                 // FFT steps fused with the following transpose
+    int fuse_kind[kMaxDims] = {};       // per step: 1 power-of-two kernel, 2 generic smooth-length unit
 
     // per-stage timing events (fft_plan_set_timing)
     bool timing = false;

@@ -224,7 +224,10 @@ def test_default_order_is_best(gpu_lib):
 
 @pytest.mark.parametrize("dims,P,oidx", [((64, 64, 64), 48, 0), ((64, 64, 64), 1000, 3), ((128, 32, 64), 7, 5),
                                          ((512, 512, 512), 4096, 0), ((16, 32, 64, 128), 300, 777),
-                                         ((32, 16, 64, 32, 16), 100, 123457), ((256, 256, 256), 64, 6)])
+                                         ((32, 16, 64, 32, 16), 100, 123457), ((256, 256, 256), 64, 6),
+                                         ((60, 48, 36), 20, 3), ((45, 50, 27, 12), 50, 400),
+                                         ((96, 80, 64), 7, 1), ((12, 15, 20, 6, 9), 64, 5000000),
+                                         ((250, 243, 6), 1000, 2)])
 @pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
 def test_fused_fft_transpose(gpu_lib, dims, P, oidx, dtype):
     if dtype == np.complex128 and np.prod(dims) > 1 << 24:
@@ -256,6 +259,8 @@ def test_fused_fft_transpose(gpu_lib, dims, P, oidx, dtype):
     print("fused" if fused else "unfused", dims, flush=True)
     if dims in ((64, 64, 64), (512, 512, 512), (256, 256, 256)) and dtype == np.complex64:
         assert fused
+    if dims in ((60, 48, 36), (45, 50, 27, 12), (12, 15, 20, 6, 9), (250, 243, 6)):
+        assert fused  # every step has 2,3,5-smooth rows: the generic fused unit
 
 
 def test_fused_leave_permuted_and_in_place(gpu_lib):
