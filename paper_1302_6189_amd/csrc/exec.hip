@@ -34,6 +34,8 @@ hipError_t launch_fft_xpose_generic(const FftDesc &f, const XposeDesc &d, bool f
                                     void *out, double scale, hipStream_t s);
 hipError_t launch_fft_xpose_pow2(int N, bool fp64, const void *tw, const XposeDesc &fx, int dir, const void *in,
                                  void *out, double scale, hipStream_t s);
+hipError_t launch_fft256_mfma_xpose(int precision, int dir, const void *tw256, const XposeDesc &d, const void *in,
+                                    void *out, double scale, hipStream_t s);
 hipError_t launch_fft256_mfma(int precision, int dir, const void *tw256, int64_t nrows, const void *in, void *out,
                               double scale, hipStream_t s);
 hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in, void *out, double scale,
@@ -309,6 +311,9 @@ int run_pipeline(fft_plan_impl *pl, const void *in, void *out, hipStream_t s, in
             if (pl->fuse_kind[t] == 1)
                 HIP_TRY(launch_fft_xpose_pow2(d.N, pl->esz == 16, d.tw, pl->xp[t], dir, src, dst, scale, s),
                         "fused fft+transpose launch");
+            else if (pl->fuse_kind[t] == 3)
+                HIP_TRY(launch_fft256_mfma_xpose(d.mfma, dir, d.tw, pl->xp[t], src, dst, scale, s),
+                        "fused mfma fft+transpose launch");
             else
                 HIP_TRY(launch_fft_xpose_generic(d, pl->xp[t], pl->esz == 16, dir, src, dst, scale, s),
                         "fused fft+transpose launch");
@@ -504,9 +509,9 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
     }
     // fusion of every FFT step with its transpose: power-of-two rows of 16..512
     // (256 in FP64) whose work-group's run of consecutive v-values fits the v
-    // axis use the compile-time kernel; 2,3,5-smooth rows use the generic unit
-    if ((flags & FFTRW_FLAG_FUSED_FFT) && !(flags & FFTRW_FLAG_STAGED) && precision == FFTRW_PREC_NATIVE &&
-        !generic_rows) {
+    // axis use the compile-time kernel; 2,3,5-smooth rows use the generic unit;
+    // steps of the split-precision form (256 points) use the MFMA kernel
+    if ((flags & FFTRW_FLAG_FUSED_FFT) && !(flags & FFTRW_FLAG_STAGED) && !generic_rows) {
         const bool fp64 = pl->esz == 16;
         const int nx = (flags & FFTRW_FLAG_LEAVE_PERMUTED) ? M - 1 : M;
         bool ok = true;
@@ -515,7 +520,7 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
             const bool pow2_ok = d.pow2 && !d.mfma && d.N >= 16 && d.N <= (fp64 ? 256 : 512) &&
                                  pow2_rows_per_wg(d.N, fp64) <= pl->xp[t].Nv;
             const bool generic_ok = !d.pow2 && !d.mfma && d.N + 1 <= (fp64 ? 2048 : 4096);
-            pl->fuse_kind[t] = pow2_ok ? 1 : (generic_ok ? 2 : 0);
+            pl->fuse_kind[t] = d.mfma ? 3 : (pow2_ok ? 1 : (generic_ok ? 2 : 0));
             ok = pl->fuse_kind[t] != 0;
         }
         pl->fused = ok;

@@ -70,3 +70,27 @@ def test_config4_256cube(gpu_lib, cube256, name, kind):
     assert dft.rel_l2(to_host(zd), x) < 2 * tol
     analytic, moved = plan.stats()
     assert moved == analytic
+
+
+@pytest.mark.parametrize("name", ["f16", "bf16", "bf16x3"])
+@pytest.mark.parametrize("dims,P,oidx", [((256, 256, 256), 64, 0), ((256, 40, 256), 7, 3),
+                                         ((256, 256, 24, 256), 300, 700)])
+def test_fused_mfma_matches_separate_steps(gpu_lib, name, dims, P, oidx):
+    # the 256-point MFMA transform fused with the transpose that follows runs the
+    # same per-row arithmetic as the separate MFMA step; N_v = 40 and 24 leave
+    # ragged groups of 16 rows
+    prec, _ = PRECS[name]
+    order = fftrw.fft_order_at(len(dims), oidx)
+    x = inputs.uniform(dims, 44, np.complex64)
+    xd = to_dev(x)
+    fused = fftrw.Plan(dims, P, order, precision=prec, flags=fftrw.FLAG_FUSED_FFT | fftrw.FLAG_COUNT_MOVED)
+    plain = fftrw.Plan(dims, P, order, precision=prec, flags=fftrw.FLAG_COUNT_MOVED)
+    desc = fused.describe()[1]
+    assert desc.startswith("fused|") and "mfma:" in desc, desc
+    for fwd in (True, False):
+        a, b = empty_dev(dims, np.complex64), empty_dev(dims, np.complex64)
+        (fused.exec_fwd if fwd else fused.exec_inv)(xd, a)
+        (plain.exec_fwd if fwd else plain.exec_inv)(xd, b)
+        assert np.array_equal(to_host(a), to_host(b)), fwd
+        an, mv = fused.stats()
+        assert mv == an
