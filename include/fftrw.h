@@ -47,9 +47,11 @@ enum {
     FFTRW_E_SIZE = -2,        /* M not in [2,5], a size < 1, or a row length the
                                  FFT kernels do not support (see fft_plan)     */
     FFTRW_E_ORDER = -3,       /* malformed permutation or transpose order      */
-    FFTRW_E_ROWSPLIT = -4,    /* N_p > T / N_last for some step: rows along the
-                                 FFT axis would be split over processes (level M
-                                 of Eq. (13)); the paper leaves that case open  */
+    FFTRW_E_ROWSPLIT = -4,    /* N_p > T (no level of Eq. (13) applies); or a
+                                 step at level M (N_p > T / N_last: rows along
+                                 its FFT axis split over processes) where whole
+                                 rows are needed (staged transposes), or as a
+                                 flag from fft_comm_volume (see there)          */
     FFTRW_E_NOMEM = -5,       /* host or device allocation failed             */
     FFTRW_E_DEVICE = -6,      /* a HIP call failed; see fft_last_error()       */
     FFTRW_E_UNSUPPORTED = -7  /* combination not implemented                   */
@@ -115,8 +117,10 @@ int fft_decomp(int M, const int64_t *dims, int64_t P, const int8_t *perm,
  *   in every decomposition.  FFTRW_OWN_MATCHED (R2): the ranges of each new
  *   decomposition are assigned to processes one-to-one so that the most
  *   points stay put (maximum-weight matching on the overlap counts).
- * Counts are exact int64.  Row-split orders (level M) are still counted, and
- * the call returns FFTRW_E_ROWSPLIT after filling the outputs.
+ * Counts are exact int64.  Row-split orders (a step at level M) are counted
+ * like any other, and the call returns FFTRW_E_ROWSPLIT after filling the
+ * outputs: the amounts then leave out whatever the split rows' own 1-D FFTs
+ * would exchange, which the paper does not define.
  */
 int fft_comm_volume(int M, const int64_t *dims, int64_t P, const int8_t *order,
                     int ownership, int64_t *per_step, int64_t *total,
@@ -181,6 +185,10 @@ int fft_compare_models(double N, double P, double *out);
  *          forms need dtype C64 and every FFT axis a power of two >= 16.
  *   flags: FFTRW_FLAG_*.
  * Row lengths: every dims[i] must factor into 2, 3, 5 and be <= 4096.
+ * 1 <= P <= T.  Steps at level M of Eq. (13) (P > T / N_last, rows split
+ * along the FFT axis) run: the processes sharing a row share device memory,
+ * so the row is transformed whole, and the transposes are counted exactly as
+ * at other levels; staged transposes refuse them (FFTRW_E_ROWSPLIT).
  * The plan owns its device workspace (fft_workspace_bytes) and twiddle
  * tables; it must outlive every exec enqueued with it.  One exec per plan may
  * be in flight at a time.

@@ -16,7 +16,8 @@ orders     Eq. (20) / Table 1: valid transpose orders and their enumeration.
 pipeline   Fig. 4 with explicit per-process arrays and an all-to-all.
 
 Parity status: every function is pinned by a test against values the paper
-prints, closed forms, textbook identities or brute force, except the handling
-of the row-split regime (level M), which the paper leaves undefined and the
-oracle refuses (parity unpinned: not implemented).
+prints, closed forms, textbook identities or brute force.  The row-split
+regime (level M) follows a stated reading in ``pipeline`` (a split row is
+transformed whole); its values are pinned by the M-D DFT, its amounts by the
+closed form at N_p = T (every point its own process).
 """

@@ -5,8 +5,14 @@ product path.
 
 N_p processes are simulated one array each.  For t = 1..M:
   * Step t: every process runs 1-D FFTs along the last axis of pi_t over the
-    whole rows it holds (they are whole because the level of Eq. (13) is
-    below M).
+    whole rows it holds (they are whole when the level of Eq. (13) is below
+    M).  At level M (N_p larger than the number of rows, the last case of
+    Eq. (13)) ranges cut rows along the FFT axis, and the paper does not say
+    how such a row is transformed.  Reading taken here: the processes that
+    share a row transform it as one row (their ranges are consecutive pieces
+    of the pi_t-order array) and each keeps its own piece; the communication
+    this needs is not part of the transposes' amounts, which are counted as
+    at any other level.
   * Transpose: each process packs its points into one segment per destination
     (the owner in the next decomposition), an all-to-all moves every segment
     whose destination is another process (counted, in points), and each
@@ -114,9 +120,6 @@ def fftn_decomposed(x: np.ndarray, P: int, order, sign: int = -1):
     dims = x.shape
     M = len(dims)
     ident = tuple(range(M))
-    for perm in order:
-        if decomp.level([dims[a] for a in perm], P) >= M:
-            raise decomp.RowSplitError("rows along the FFT axis would be split")
     b0 = decomp.boundaries(dims, P, ident)
     flat = x.reshape(-1)
     local = [flat[b0[p]:b0[p + 1]].copy() for p in range(P)]
@@ -125,7 +128,13 @@ def fftn_decomposed(x: np.ndarray, P: int, order, sign: int = -1):
     for t in range(M):
         perm = order[t]
         n_last = int(dims[perm[-1]])
-        local = [fft1d_rows(a.reshape(-1, n_last), sign).reshape(-1) for a in local]
+        if decomp.level([dims[a] for a in perm], P) < M:
+            local = [fft1d_rows(a.reshape(-1, n_last), sign).reshape(-1) for a in local]
+        else:
+            # level M: split rows are transformed whole, pieces stay in place
+            sizes = [a.size for a in local]
+            whole = fft1d_rows(np.concatenate(local).reshape(-1, n_last), sign).reshape(-1)
+            local = np.split(whole, np.cumsum(sizes)[:-1])
         nxt = order[t + 1] if t + 1 < M else ident
         local, moved = _transpose(local, dims, P, perm, nxt)
         if t + 1 < M:

@@ -225,14 +225,14 @@ int make_xpose_desc(fft_plan_impl *pl, const Layout &a, const Layout &b, const s
     d->owner32 = (__int128)a.R * pl->P < ((__int128)1 << 32) && (__int128)b.R * pl->P < ((__int128)1 << 32);
     for (int j = 0; j < a.k; ++j) {
         const int ax = a.perm[j];
-        d->srca[j] = ax == v ? 3 : batpos[ax];
+        d->srca[j] = ax == v ? 3 : ax == u ? 4 : batpos[ax];
         i64 w = 1;
         for (int i = j + 1; i < a.k; ++i) w *= a.pd[i];
         d->wa[j] = w;
     }
     for (int j = 0; j < b.k; ++j) {
         const int ax = b.perm[j];
-        d->srcb[j] = ax == u ? 4 : batpos[ax];
+        d->srcb[j] = ax == u ? 4 : ax == v ? 3 : batpos[ax];
         i64 w = 1;
         for (int i = j + 1; i < b.k; ++i) w *= b.pd[i];
         d->wb[j] = w;
@@ -416,10 +416,6 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
         if (!st) {
             free_plan(pl);
             return fail(st);
-        }
-        if (t < M && pl->lay[t].row_split()) {
-            free_plan(pl);
-            return fail(FFTRW_E_ROWSPLIT, "P exceeds the rows available along some FFT axis (level M)");
         }
     }
     // analytic amounts (and relabellings for the matched reading)

@@ -18,6 +18,7 @@
 
 #include "cplx.hpp"
 #include "kernels.hpp"
+#include "xpose_tile.hpp"
 
 namespace fftrw {
 
@@ -228,13 +229,7 @@ __global__ void __launch_bounds__(kThreads)
 // consecutive in v (the last axis of layout B) within one batch slice, then
 // writes the results in layout B: the last pass lands in an LDS staging block
 // S[k][r] and each k becomes one run of RW consecutive v-values in HBM.  Owner
-// counting as in the transpose: A's owner is constant along a row, B's along
-// a run.
-__device__ __forceinline__ int64_t fx_owner(int64_t r, int64_t P, int64_t R, bool narrow)
-{
-    if (narrow) return (int64_t)(((uint32_t)(r + 1) * (uint32_t)P - 1u) / (uint32_t)R);
-    return ((r + 1) * P - 1) / R;
-}
+// counting as in the transpose (row_keep).
 
 // threads per work-group of the fused kernel: 512 when a 256-thread group
 // would hold fewer than 16 rows (runs of 16 values = 128 bytes)
@@ -296,37 +291,12 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
             for (int e = 0; e < E; ++e) v[e] = mk<C>(0, 0);
         }
     }
-    // (computed while the row loads are in flight) owner changes of this group's rows: row v keeps the k whose row index in
-    // B falls inside the range of v's owner (B's owner is monotone in k), an
-    // interval count; the rest move
+    // (computed while the row loads are in flight) owner changes of this
+    // group's rows: thread r counts row v0 + r
     int moved = 0;
     if (d.count) {
         if (threadIdx.x == 0) moved_wg = 0;
-        if (threadIdx.x < nv) {
-            const bool narrow = d.owner32 != 0;
-            const int r = threadIdx.x;
-            int64_t row = 0;
-            for (int j = 0; j < d.ka; ++j) row += (d.srca[j] == 3 ? v0 + r : (int64_t)bc[d.srca[j]]) * d.wa[j];
-            int64_t o = fx_owner(row, d.P, d.Ra, narrow);
-            if (d.mu) o = d.mu[o];
-            int64_t rb0 = 0, wk = 0;
-            for (int j = 0; j < d.kb; ++j) {
-                if (d.srcb[j] == 4)
-                    wk = d.wb[j];
-                else
-                    rb0 += (int64_t)bc[d.srcb[j]] * d.wb[j];
-            }
-            int64_t keep;
-            if (wk == 0) {
-                keep = fx_owner(rb0, d.P, d.Rb, narrow) == o ? N : 0;
-            } else {
-                const int64_t lo = (d.Rb * o) / d.P - rb0, hi = (d.Rb * (o + 1)) / d.P - rb0;
-                auto cdiv = [&](int64_t x) { return x >= 0 ? (x + wk - 1) / wk : x / wk; };
-                const int64_t k0 = max<int64_t>(0, cdiv(lo)), k1 = min<int64_t>(N, cdiv(hi));
-                keep = max<int64_t>(0, k1 - k0);
-            }
-            moved = (int)(N - keep);
-        }
+        if (threadIdx.x < nv) moved = (int)(N - row_keep(d, bc, v0 + threadIdx.x, 0, N));
     }
 
     run_passes<N, E, DIR, RL, 0>(v, lds + r * (N + N / 16), lane, tw);

@@ -50,6 +50,7 @@ struct XposeDesc {
     int count;
     int ka, kb;              // levels of A and B
     int srca[5], srcb[5];    // for each leading axis: 0..2 batch index, 3 = v, 4 = u
+                             // (u leads in A and v in B only at level M)
     int64_t wa[5], wb[5];    // row-index weights of the leading axes
     int64_t Ra, Rb, P;
     int owner32;             // (r+1) P - 1 fits in 32 bits for both layouts

@@ -11,12 +11,15 @@
 // thread moves two neighbouring values per 16-byte access.
 //
 // Owner counting: virtual process p owns a contiguous range of rows over the
-// first k axes of its decomposition (Eqs. (13)-(15)).  The first k axes of A
-// never include u and those of B never include v (k < M), so inside a tile
-// A's owner depends only on (slice, v) and B's only on (slice, u), and B's
-// row index grows linearly with u.  For each (slice, v) the points that keep
-// their owner are the u whose B row falls in that owner's range, an interval;
-// the rest of the row moves.  Summed over tiles this is the paper's
+// first k axes of its decomposition (Eqs. (13)-(15)).  Below level M the
+// first k axes of A never include u and those of B never include v, so along
+// a (slice, v) row A's owner is fixed and B's row index grows linearly with u:
+// the points that keep their owner are the u whose B row falls in that
+// owner's range, an interval.  At level M (more processes than rows, the last
+// case of Eq. (13)) the row index is the point's whole linear index, so A's
+// owner also grows with u (and B's row index also depends on v); the row then
+// splits into pieces of constant A owner, each counted the same way (row_keep).
+// The rest of the row moves.  Summed over tiles this is the paper's
 // communication amount for the transpose.
 #pragma once
 
@@ -77,7 +80,8 @@ __device__ __forceinline__ void slice_coords(const XposeDesc &d, int64_t s, int 
 }
 
 // Owner vectors of one tile: A's over (slice, v) into own_a[g * TV + iv], B's
-// over (slice, u) into own_b[g * TU + iu] (slices g0 .. g0 + ng - 1).
+// over (slice, u) into own_b[g * TU + iu] (slices g0 .. g0 + ng - 1).  Below
+// level M only (the staged transposes, which need whole rows).
 __device__ __forceinline__ void tile_owners(const XposeDesc &d, int64_t g0, int ng, int64_t u0, int nu, int64_t v0,
                                             int nv, int *own_a, int *own_b)
 {
@@ -110,46 +114,66 @@ __device__ __forceinline__ void tile_owners(const XposeDesc &d, int64_t g0, int 
     }
 }
 
-// Points of one tile whose owner changes, this thread's share: for each
-// (slice, v) row, A's owner o is fixed and B's owner is monotone in u, so the
-// u that stay with o are those whose row index in B lies in o's range -- an
-// interval count, no per-point comparison.
+// Points of the row (batch coordinates c, v) with u in [u0, u0 + nu) that keep
+// their owner.  Both row indices are affine in u: B's grows with u when u is
+// one of B's leading axes, A's only at level M.  Owners are monotone in the
+// row index, so the row is a sequence of pieces of constant A owner o, and
+// inside a piece the u whose B row lies in o's range form an interval.
+__device__ __forceinline__ int64_t row_keep(const XposeDesc &d, const int *c, int64_t v, int64_t u0, int64_t nu)
+{
+    const bool narrow = d.owner32 != 0;
+    int64_t ra0 = 0, wau = 0, rb0 = 0, wbu = 0;
+    for (int j = 0; j < d.ka; ++j) {
+        const int src = d.srca[j];
+        if (src == 4)
+            wau = d.wa[j];
+        else
+            ra0 += (src == 3 ? v : (int64_t)c[src]) * d.wa[j];
+    }
+    for (int j = 0; j < d.kb; ++j) {
+        const int src = d.srcb[j];
+        if (src == 4)
+            wbu = d.wb[j];
+        else
+            rb0 += (src == 3 ? v : (int64_t)c[src]) * d.wb[j];
+    }
+    // ceil(x / w) for w > 0 (integer division truncates towards zero)
+    auto cdiv = [](int64_t x, int64_t w) { return x >= 0 ? (x + w - 1) / w : x / w; };
+    // u in [a, b) whose B row lies in the range of process o
+    auto keep_b = [&](int64_t o, int64_t a, int64_t b) -> int64_t {
+        if (wbu == 0) return owner_of_row(rb0, d.P, d.Rb, narrow) == o ? b - a : 0;
+        const int64_t lo = (d.Rb * o) / d.P - rb0, hi = (d.Rb * (o + 1)) / d.P - rb0;
+        const int64_t k0 = max<int64_t>(a, cdiv(lo, wbu)), k1 = min<int64_t>(b, cdiv(hi, wbu));
+        return max<int64_t>(0, k1 - k0);
+    };
+    if (wau == 0) {
+        int64_t o = owner_of_row(ra0, d.P, d.Ra, narrow);
+        if (d.mu) o = d.mu[o];
+        return keep_b(o, u0, u0 + nu);
+    }
+    int64_t keep = 0;
+    for (int64_t u = u0, end = u0 + nu; u < end;) {
+        const int64_t oa = owner_of_row(ra0 + u * wau, d.P, d.Ra, narrow);
+        // first u past this piece: A row reaches the start of range oa + 1
+        const int64_t next = min<int64_t>(end, cdiv((d.Ra * (oa + 1)) / d.P - ra0, wau));
+        keep += keep_b(d.mu ? (int64_t)d.mu[oa] : oa, u, next);
+        u = next;
+    }
+    return keep;
+}
+
+// Points of one tile whose owner changes, this thread's share (one (slice, v)
+// row at a time).
 __device__ __forceinline__ int tile_moved(const XposeDesc &d, int64_t g0, int ng, int64_t u0, int nu, int64_t v0,
                                           int nv)
 {
-    const bool narrow = d.owner32 != 0;
     int moved = 0;
     for (int i = threadIdx.x; i < ng * nv; i += kThreads) {
         const int g = i / nv, iv = i - g * nv;
         int c[3];
         int64_t ab, bb;
         slice_coords(d, g0 + g, c, &ab, &bb);
-        int64_t r = 0;
-        for (int j = 0; j < d.ka; ++j) {
-            const int src = d.srca[j];
-            r += (src == 3 ? v0 + iv : (int64_t)c[src]) * d.wa[j];
-        }
-        int64_t o = owner_of_row(r, d.P, d.Ra, narrow);
-        if (d.mu) o = d.mu[o];
-        int64_t rb0 = 0, wu = 0;
-        for (int j = 0; j < d.kb; ++j) {
-            const int src = d.srcb[j];
-            if (src == 4)
-                wu = d.wb[j];
-            else
-                rb0 += (int64_t)c[src] * d.wb[j];
-        }
-        int64_t keep;
-        if (wu == 0) {
-            keep = owner_of_row(rb0, d.P, d.Rb, narrow) == o ? nu : 0;
-        } else {
-            // u in [u0, u0 + nu) with row_lo(o) <= rb0 + u wu < row_lo(o + 1)
-            const int64_t lo = (d.Rb * o) / d.P - rb0, hi = (d.Rb * (o + 1)) / d.P - rb0;
-            auto cdiv = [&](int64_t x) { return x >= 0 ? (x + wu - 1) / wu : x / wu; };
-            const int64_t k0 = max<int64_t>(u0, cdiv(lo)), k1 = min<int64_t>(u0 + nu, cdiv(hi));
-            keep = max<int64_t>(0, k1 - k0);
-        }
-        moved += nu - (int)keep;
+        moved += nu - (int)row_keep(d, c, v0 + iv, u0, nu);
     }
     return moved;
 }

@@ -152,8 +152,8 @@ def test_config3_orders(gpu_lib, dims, P, oidx, staged):
     try:
         plan = fftrw.Plan(dims, P, order, flags=fftrw.FLAG_COUNT_MOVED | extra)
     except fftrw.FftrwError as e:
-        assert e.code == fftrw.E_ROWSPLIT
-        pytest.skip("row-split order")
+        assert e.code == fftrw.E_ROWSPLIT and staged
+        pytest.skip("staged transposes need whole rows")
     x = inputs.gaussian(dims, 3 if M == 4 else 30, np.complex64)
     xd = to_dev(x)
     yd = empty_dev(dims, np.complex64)
@@ -200,7 +200,10 @@ def test_plan_errors_on_device(gpu_lib):
         fftrw.Plan((7, 8, 8), 2, "abc->acb->bca")
     assert e.value.code == fftrw.E_SIZE
     with pytest.raises(fftrw.FftrwError) as e:
-        fftrw.Plan((8, 8, 8), 65, "abc->acb->bca")
+        fftrw.Plan((8, 8, 8), 513, "abc->acb->bca")  # more processes than points
+    assert e.value.code == fftrw.E_ROWSPLIT
+    with pytest.raises(fftrw.FftrwError) as e:
+        fftrw.Plan((8, 8, 8), 65, "abc->acb->bca", flags=fftrw.FLAG_STAGED)  # level M, staged
     assert e.value.code == fftrw.E_ROWSPLIT
     with pytest.raises(fftrw.FftrwError) as e:
         fftrw.Plan((8, 8, 8), 4, "abc->acb->bca", dtype=3)
