@@ -127,6 +127,23 @@ int fft_comm_volume(int M, const int64_t *dims, int64_t P, const int8_t *order,
                     int64_t *return_volume);
 
 /*
+ * fft_rowsplit_volume -- what the 1-D FFTs of split rows would exchange, for
+ * the steps at level M of Eq. (13) (N_p > T / N_last), which the transposes'
+ * amount leaves out.  The paper does not say how a split row is transformed;
+ * the reading here is a binary exchange: a row of length N held by c > 1
+ * processes runs ceil(log2 c) butterfly stages whose partners sit on other
+ * processes, each sending every point of the row once, so the row adds
+ * N * ceil(log2 c) points.  With it the 64^3 comparison of Section 4 against
+ * the 3-D method (Eq. (23)) peaks at 8,192 processes at 11.6 times.
+ *   per_step[M] (nullable): one count per FFT step t = 1..M (0 below level M).
+ *   total: their sum.
+ * Errors: FFTRW_E_ARG, FFTRW_E_SIZE, FFTRW_E_ORDER, FFTRW_E_ROWSPLIT if P > T.
+ * Cost O(M * P) on the host.
+ */
+int fft_rowsplit_volume(int M, const int64_t *dims, int64_t P, const int8_t *order,
+                        int64_t *per_step, int64_t *total);
+
+/*
  * fft_pair_counts -- overlap counts C[p][q] = points owned by p in
  * decomposition perm_a and by q in perm_b (literal ownership), written densely
  * into C[P*P] (host, caller-owned).  For checking; P <= 4096.

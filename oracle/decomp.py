@@ -184,6 +184,30 @@ def order_volumes(dims, P: int, order, ownership: str = "literal"):
 # ----------------------------------------------------------------------------
 # Comparison models, Eqs. (21)-(25), evaluated as printed in real arithmetic.
 # ----------------------------------------------------------------------------
+def split_row_volume(dims, P: int, perm) -> int:
+    """Points the 1-D FFTs along the last axis of ``perm`` would exchange when
+    that decomposition is at level M, under the binary-exchange reading (the
+    paper does not say how a split row is transformed): a row held by c > 1
+    processes runs ceil(log2 c) butterfly stages across processes, each
+    sending all N points of the row.  0 below level M."""
+    pdims = [int(dims[a]) for a in perm]
+    M = len(pdims)
+    if level(pdims, P) < M:
+        return 0
+    N = pdims[-1]
+    # owners of every point in the layout of perm, row by row
+    b = boundaries(dims, P, perm)
+    x = np.arange(prod(pdims), dtype=np.int64)
+    own = np.sort((np.searchsorted(b, x, side="right") - 1).reshape(-1, N), axis=1)
+    distinct = 1 + np.count_nonzero(np.diff(own, axis=1), axis=1)   # processes per row
+    return int(sum(N * (int(c) - 1).bit_length() for c in distinct))   # ceil(log2 c) for c >= 1
+
+
+def order_split_volumes(dims, P: int, order):
+    """split_row_volume of each FFT step of an order."""
+    return [split_row_volume(dims, P, perm) for perm in order]
+
+
 def amount_1d_method(N: float, Np: float) -> float:
     """Eq. (21): slab method, N^3 - N^3/N_p."""
     return N ** 3 - N ** 3 / Np

@@ -152,6 +152,51 @@ int fft_comm_volume(int M, const int64_t *dims, int64_t P, const int8_t *order, 
     return FFTRW_OK;
 }
 
+int fft_rowsplit_volume(int M, const int64_t *dims, int64_t P, const int8_t *order, int64_t *per_step,
+                        int64_t *total)
+{
+    g_last_error.clear();
+    if (!total) return fail(FFTRW_E_ARG, "total must not be null");
+    Status s = check_dims(M, dims);
+    if (!s) return fail(s);
+    s = check_order(M, order);
+    if (!s) return fail(s);
+    // stages of a binary exchange over c processes: ceil(log2 c)
+    auto stages = [](i64 c) {
+        int n = 0;
+        while (((i64)1 << n) < c) ++n;
+        return (i64)n;
+    };
+    i64 sum = 0;
+    for (int t = 0; t < M; ++t) {
+        Layout L;
+        s = make_layout(M, dims, P, order + t * M, &L);
+        if (!s) return fail(s);
+        i64 v = 0;
+        if (L.row_split()) {
+            // a row of the FFT axis holds 1 + (boundaries strictly inside it)
+            // processes: walk the process boundaries, not the rows
+            const i64 N = L.pd[M - 1];
+            i64 row = -1, inside = 0;
+            for (i64 p = 1; p < P; ++p) {
+                const i64 b = L.boundary(p);
+                if (b % N == 0) continue;
+                if (b / N != row) {
+                    if (row >= 0) v += N * stages(inside + 1);
+                    row = b / N;
+                    inside = 0;
+                }
+                ++inside;
+            }
+            if (row >= 0) v += N * stages(inside + 1);
+        }
+        if (per_step) per_step[t] = v;
+        sum += v;
+    }
+    *total = sum;
+    return FFTRW_OK;
+}
+
 int fft_pair_counts(int M, const int64_t *dims, int64_t P, const int8_t *perm_a, const int8_t *perm_b,
                     int64_t *C)
 {

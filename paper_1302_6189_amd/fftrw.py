@@ -53,6 +53,7 @@ _SIGNATURES = {
                                   ctypes.POINTER(ctypes.c_int), _i64p, _i64p, _i64p, _i64p]),
     "fft_comm_volume": (ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, _i8p, ctypes.c_int,
                                        _i64p, _i64p, _i64p]),
+    "fft_rowsplit_volume": (ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, _i8p, _i64p, _i64p]),
     "fft_pair_counts": (ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, _i8p, _i8p, _i64p]),
     "fft_order_count": (ctypes.c_int64, [ctypes.c_int]),
     "fft_order_at": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, _i8p]),
@@ -174,6 +175,17 @@ def fft_comm_volume(dims, P, order, ownership=OWN_LITERAL, allow_rowsplit=False)
     if not (allow_rowsplit and rc == E_ROWSPLIT):
         _check(rc)
     return list(per), tot.value, ret.value
+
+
+def fft_rowsplit_volume(dims, P, order):
+    """(per FFT step list, total): points the split rows' own 1-D FFTs would
+    exchange at level M under the binary-exchange reading (0 below level M)."""
+    M = len(dims)
+    order = order_from(order, M)
+    per = (ctypes.c_int64 * M)()
+    tot = ctypes.c_int64()
+    _check(lib().fft_rowsplit_volume(M, _dims(dims), int(P), _order(order), per, ctypes.byref(tot)))
+    return list(per), tot.value
 
 
 def fft_pair_counts(dims, P, perm_a, perm_b):

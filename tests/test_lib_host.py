@@ -197,6 +197,19 @@ def test_error_codes():
     assert e.value.code == fftrw.E_ROWSPLIT
 
 
+@pytest.mark.parametrize("dims,P", [((8, 8, 8), 100), ((16, 8, 4), 100), ((6, 5, 4), 77), ((8, 8, 8, 8), 1000),
+                                    ((3, 4, 5, 2, 3), 200), ((4, 4, 4), 64), ((12, 10, 9), 500)])
+def test_rowsplit_volume_matches_oracle(dims, P):
+    M = len(dims)
+    rng = random.Random(P)
+    n = fftrw.fft_order_count(M)
+    for idx in rng.sample(range(n), min(n, 12)):
+        o = fftrw.fft_order_at(M, idx)
+        per, tot = fftrw.fft_rowsplit_volume(dims, P, o)
+        assert per == decomp.order_split_volumes(dims, P, o), fftrw.order_to_str(o)
+        assert tot == sum(per)
+
+
 def test_comparison_with_five_d_method_via_library():
     # Section 4: on 16^5 the method needs up to ~11.1x less than the 5-D method
     # (Eq. (25)).  Each distinct transpose amount identity -> rho is read from

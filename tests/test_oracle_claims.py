@@ -203,6 +203,27 @@ def test_comparison_with_two_d_method():
         assert P >= c["vs2d_64cube_gap_zero_from"] and gain[P] < 0.005
 
 
+def test_comparison_with_three_d_method_row_split():
+    # Section 4: beyond 4,096 processes only the 3-D method (Eq. (23)) and this
+    # one work on 64^3, and every decomposition is at level M.  With the split
+    # rows' own FFTs done by binary exchange (ceil(log2 c) all-point stages for
+    # a row over c processes) the advantage peaks at 8,192 processes, 11.6x.
+    c = _claims()
+    N = 64
+    dims = (N, N, N)
+    Ps = [8192 * 2 ** j for j in range(6)]
+    st = study(3, N, Ps)
+    ratio = {}
+    for P in Ps:
+        split = {p: decomp.split_row_volume(dims, P, p) for p in st.perms}
+        tot = st.res[P] + np.array([sum(split[st.perms[i]] for i in row) for row in st.seq])
+        ratio[P] = decomp.amount_3d_method(N, P) / tot.min()
+    assert round(ratio[8192], 1) == c["vs3d_64cube_max_at_8192"]
+    assert max(ratio, key=ratio.get) == 8192
+    # the transposes alone would give 29.2x: the split rows' exchanges matter
+    assert round(decomp.amount_3d_method(N, 8192) / st.res[8192].min(), 1) == 29.2
+
+
 def test_comparison_with_four_d_method():
     c = _claims()
     N = 16

@@ -184,3 +184,38 @@ def test_permute_layout_is_a_transpose():
     assert y.shape == (4, 2, 3) and y[3, 1, 2] == x[1, 2, 3]
     z = pipeline.permute_layout(y, (2, 0, 1), (1, 2, 0))
     assert z.shape == (3, 4, 2) and z[2, 3, 1] == x[1, 2, 3]
+
+
+@pytest.mark.parametrize("dims,P,want", [((8, 8, 8), 128, 512), ((8, 8, 8), 512, 1536), ((4, 4, 4, 4), 256, 512),
+                                         ((8, 8, 8), 64, 0), ((2, 4, 8, 4), 32, 0)])
+def test_split_row_volume_closed_form(dims, P, want):
+    # powers of two, equal rows: every row of N points is split over
+    # s = P N / T processes and sends N log2(s) points (0 below level M)
+    for perm in _perms(len(dims))[:6]:
+        assert decomp.split_row_volume(dims, P, perm) == want
+
+
+def test_split_row_volume_mixed_levels():
+    # (8, 4, 2) over 32 processes: rows along 8 are split over 4 processes,
+    # along 4 over 2, rows along 2 stay whole (level 2)
+    dims, P = (8, 4, 2), 32
+    for perm in _perms(3):
+        n_last = dims[perm[-1]]
+        assert decomp.split_row_volume(dims, P, perm) == {8: 64 * 2, 4: 64 * 1, 2: 0}[n_last]
+
+
+@pytest.mark.parametrize("dims,P", [((4, 4, 4), 20), ((6, 5, 4), 50), ((3, 4, 2, 5), 77), ((2, 3, 2, 2, 3), 40)])
+def test_split_row_volume_from_ranges(dims, P):
+    # ragged: processes per row counted from the ranges of Eqs. (14)-(15)
+    # (which processes' [x^s, x^e] meet the row), not from point owners
+    M = len(dims)
+    for perm in _perms(M)[:8]:
+        pd = [dims[a] for a in perm]
+        N, T = pd[-1], prod(pd)
+        rng = [decomp.decomp(dims, P, perm, p)[1:3] for p in range(P)]
+        want = 0
+        if decomp.level(pd, P) == M:
+            for r in range(T // N):
+                c = sum(1 for xs, xe in rng if xs <= r * N + N - 1 and xe >= r * N)
+                want += N * (c - 1).bit_length()
+        assert decomp.split_row_volume(dims, P, perm) == want
