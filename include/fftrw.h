@@ -13,7 +13,11 @@
  *
  * Conventions used by every entry point
  * -------------------------------------
- * - M in [2, 5]; dims[0..M) = (N_1, ..., N_M), N_1 slowest (row-major, C order).
+ * - M in [2, 5] for plans, batches and the autotuner; the host functions on
+ *   ranges, amounts and orders (fft_decomp, fft_comm_volume,
+ *   fft_rowsplit_volume, fft_pair_counts, fft_transpose_volumes,
+ *   fft_order_*) also take M = 6.  dims[0..M) = (N_1, ..., N_M), N_1 slowest
+ *   (row-major, C order).
  * - An axis permutation `perm` (M int8) lists natural axis indices from the
  *   slowest to the fastest position: {2,0,1} is the paper's "cab".
  * - A transpose order `order` (M*M int8) is M permutations, row t = pi_{t+1}:
@@ -44,8 +48,9 @@ extern "C" {
 enum {
     FFTRW_OK = 0,
     FFTRW_E_ARG = -1,         /* null pointer, bad enum, bad index            */
-    FFTRW_E_SIZE = -2,        /* M not in [2,5], a size < 1, or a row length the
-                                 FFT kernels do not support (see fft_plan)     */
+    FFTRW_E_SIZE = -2,        /* M out of range (see conventions), a size < 1,
+                                 or a row length the FFT kernels do not support
+                                 (see fft_plan)                                */
     FFTRW_E_ORDER = -3,       /* malformed permutation or transpose order      */
     FFTRW_E_ROWSPLIT = -4,    /* N_p > T (no level of Eq. (13) applies); or a
                                  step at level M (N_p > T / N_last: rows along
@@ -164,8 +169,24 @@ int fft_order_at(int M, int64_t index, int8_t *order);
 int fft_order_index(int M, const int8_t *order, int64_t *index);
 
 /*
- * fft_order_search -- exhaustive search over all (M-1)!^M orders for the
- * smallest and largest total communication amount (Sections 3.1, 3.3).
+ * fft_transpose_volumes -- the amount of every single transpose
+ * pi_a -> pi_b that an order can contain (Sections 3.1, 3.3), as a table over
+ * the M! permutations in lexicographic order: table[a * M! + b] (host array of
+ * (M!)^2 int64, caller-owned).  Pairs no order contains are -1: two
+ * permutations with the same last axis, and pairs that involve a permutation
+ * other than the identity ending with the identity's last axis.  The amount of
+ * an order is the sum of its M-1 entries.  Computed on several host threads.
+ */
+int fft_transpose_volumes(int M, const int64_t *dims, int64_t P, int ownership,
+                          int64_t *table);
+
+/*
+ * fft_order_search -- the smallest and largest total communication amount
+ * over all (M-1)!^M orders (Sections 3.1, 3.3; for 6-D, 2,985,984,000,000
+ * orders, which Section 3.3 leaves unsearched).  Exact, without listing the
+ * orders: the amount of an order is a sum over consecutive decompositions, so
+ * a dynamic program over (current decomposition, axes already transformed)
+ * gives the optimum and the number of orders attaining it.
  * Ties go to the lowest canonical index; n_best / n_worst count the tied
  * orders.  best_order / worst_order (M*M int8, nullable) receive the orders.
  * The best order is the one fft_plan uses when given order == NULL.
@@ -177,7 +198,8 @@ int fft_order_search(int M, const int64_t *dims, int64_t P, int ownership,
 
 /*
  * fft_order_volumes -- total amount of every order (host array of
- * fft_order_count(M) int64, in canonical order).
+ * fft_order_count(M) int64, in canonical order).  M <= 5
+ * (FFTRW_E_UNSUPPORTED for 6-D: use fft_order_search).
  */
 int fft_order_volumes(int M, const int64_t *dims, int64_t P, int ownership,
                       int64_t *volumes);

@@ -85,3 +85,29 @@ def is_valid_order(order, M: int) -> bool:
 def fft_axis_sequence(order):
     """Axis transformed at each step (the last axis of each decomposition)."""
     return [p[-1] for p in order]
+
+
+def form_orders(M: int, m1: int):
+    """The orders of the form m1+m2 (m2 = M - m1), the shape Section 3.3 gives
+    the best orders: with X the first m1 axes and Y the other m2,
+    decompositions 1..m2 start with X in natural order and arrange Y after it
+    (so their FFTs run along Y's axes); decompositions m2+1..M start with one
+    common arrangement of Y and arrange X after it (FFTs along X's axes).
+    3-D a(bc) is 1+2 (abc->acb->cba), (ab)c is 2+1 (abc->cab->cba); 4-D
+    (ab)(cd) is 2+2 (abcd->abdc->dcba->dcab).  Built directly; sorted."""
+    X = tuple(range(m1))
+    Y = tuple(range(m1, M))
+    m2 = M - m1
+    ys = list(itertools.permutations(Y))
+    xs = list(itertools.permutations(X))
+    out = []
+    for rest in itertools.product(ys, repeat=m2 - 1):
+        first = [Y] + list(rest)
+        if len({p[-1] for p in first}) != m2:
+            continue
+        for lead in ys:
+            for second in itertools.product(xs, repeat=m1):
+                if len({p[-1] for p in second}) != m1:
+                    continue
+                out.append(tuple(X + p for p in first) + tuple(lead + q for q in second))
+    return sorted(out)

@@ -251,6 +251,7 @@ extern "C" int fft_autotune(int n, const fft_item_desc *items, const char *cache
     std::set<std::pair<int, int>> pairs;
     for (int i = 0; i < n; ++i) {
         const fft_item_desc &it = items[i];
+        if (it.M < 2 || it.M > kMaxDims) return fail(FFTRW_E_SIZE, "items have M = 2..5");
         Status st = check_dims(it.M, it.dims);
         if (!st) return fail(st);
         std::vector<int8_t> order(it.M * it.M);

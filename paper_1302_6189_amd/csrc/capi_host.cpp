@@ -1,10 +1,12 @@
 // capi_host.cpp -- the host-only half of the C ABI (include/fftrw.h):
 // decomposition maps, communication amounts, transpose orders, comparison
 // models.  No HIP calls here, so these work on a machine without a GPU.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/fftrw.h"
@@ -34,9 +36,9 @@ namespace {
 template <class F>
 void enumerate_orders(int M, const std::vector<std::vector<int8_t>> &perms, F &&f)
 {
-    int idx[kMaxDims];
+    int idx[kMaxHostDims];
     idx[0] = 0;  // identity is the first permutation in lexicographic order
-    bool used[kMaxDims] = {};
+    bool used[kMaxHostDims] = {};
     used[M - 1] = true;
     i64 counter = 0;
     auto rec = [&](auto &&self, int s) -> void {
@@ -76,6 +78,30 @@ struct PairTable {
         }
         vol.assign(perms.size() * perms.size(), -1);
     }
+    // Computes the listed pairs on several host threads (the amounts are
+    // independent; each entry is written by one thread).
+    void fill(const std::vector<std::pair<int, int>> &pairs)
+    {
+        const size_t nt = std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency()));
+        std::vector<Status> st(nt);
+        std::vector<std::thread> th;
+        for (size_t w = 0; w < nt; ++w)
+            th.emplace_back([&, w] {
+                for (size_t i = w; i < pairs.size(); i += nt) {
+                    const int a = pairs[i].first, b = pairs[i].second;
+                    i64 moved = 0;
+                    Status s = transpose_amount(layouts[a], layouts[b], ownership, &moved, nullptr);
+                    if (!s) {
+                        st[w] = s;
+                        return;
+                    }
+                    vol[(size_t)a * perms.size() + b] = moved;
+                }
+            });
+        for (auto &t : th) t.join();
+        for (const Status &s : st)
+            if (!s && status.code == 0) status = s;
+    }
     i64 get(int a, int b)
     {
         i64 &v = vol[(size_t)a * perms.size() + b];
@@ -87,6 +113,110 @@ struct PairTable {
         }
         return v;
     }
+};
+
+// Best and worst orders by dynamic programming.  The amount of an order is a
+// sum over its consecutive decompositions, so the optimum over all
+// (M-1)!^M orders follows from the optimal completion of each state: the
+// current decomposition a and the set U of axes already transformed (a bit
+// mask).  A completion of (a, U) continues with any b whose last axis is not
+// in U.  The number of optimal orders adds up over the same recursion.  The
+// canonical enumeration is lexicographic in permutation indices, so the
+// lowest-index optimal order is found by walking forward and taking, at each
+// step, the smallest b whose completion attains the optimum.
+struct OrderSearch {
+    int M = 0;
+    size_t np = 0;
+    std::vector<int> last;
+    std::vector<i64> val[2], cnt[2];  // [0] least, [1] largest completion amount; index a << M | U
+
+    // needed pairs: the identity (index 0) only starts an order, and no later
+    // decomposition ends with the identity's last axis
+    static std::vector<std::pair<int, int>> pairs(int M, const std::vector<std::vector<int8_t>> &perms)
+    {
+        std::vector<std::pair<int, int>> out;
+        for (size_t a = 0; a < perms.size(); ++a) {
+            if (a != 0 && perms[a][M - 1] == M - 1) continue;
+            for (size_t b = 1; b < perms.size(); ++b)
+                if (perms[b][M - 1] != M - 1 && perms[b][M - 1] != perms[a][M - 1]) out.push_back({(int)a, (int)b});
+        }
+        return out;
+    }
+
+    void run(int M_, const std::vector<std::vector<int8_t>> &perms, PairTable &tab)
+    {
+        M = M_;
+        np = perms.size();
+        const int full = (1 << M) - 1;
+        last.resize(np);
+        for (size_t a = 0; a < np; ++a) last[a] = perms[a][M - 1];
+        for (int k = 0; k < 2; ++k) {
+            val[k].assign(np << M, -1);
+            cnt[k].assign(np << M, 0);
+        }
+        // masks with more bits first: every completion refers to a larger mask
+        std::vector<int> masks;
+        for (int U = 1; U <= full; ++U)
+            if (U & (1 << (M - 1))) masks.push_back(U);
+        std::sort(masks.begin(), masks.end(),
+                  [](int x, int y) { return __builtin_popcount(x) > __builtin_popcount(y); });
+        for (int U : masks) {
+            for (size_t a = 0; a < np; ++a) {
+                if (!(U & (1 << last[a]))) continue;
+                if (last[a] == M - 1 && (a != 0 || U != (1 << (M - 1)))) continue;
+                const size_t s = (a << M) | (size_t)U;
+                if (U == full) {
+                    for (int k = 0; k < 2; ++k) {
+                        val[k][s] = 0;
+                        cnt[k][s] = 1;
+                    }
+                    continue;
+                }
+                for (size_t b = 0; b < np; ++b) {
+                    if (U & (1 << last[b])) continue;
+                    const size_t nx = (b << M) | (size_t)(U | (1 << last[b]));
+                    const i64 v = tab.get((int)a, (int)b) + val[0][nx];
+                    const i64 w = tab.get((int)a, (int)b) + val[1][nx];
+                    if (val[0][s] < 0 || v < val[0][s]) {
+                        val[0][s] = v;
+                        cnt[0][s] = cnt[0][nx];
+                    } else if (v == val[0][s]) {
+                        cnt[0][s] += cnt[0][nx];
+                    }
+                    if (val[1][s] < 0 || w > val[1][s]) {
+                        val[1][s] = w;
+                        cnt[1][s] = cnt[1][nx];
+                    } else if (w == val[1][s]) {
+                        cnt[1][s] += cnt[1][nx];
+                    }
+                }
+            }
+        }
+    }
+
+    // the lowest-index order attaining optimum k, as permutation indices
+    std::vector<int> walk(int k, PairTable &tab) const
+    {
+        std::vector<int> seq{0};
+        int U = 1 << (M - 1);
+        size_t a = 0;
+        for (int t = 1; t < M; ++t) {
+            const i64 want = val[k][(a << M) | (size_t)U];
+            for (size_t b = 0; b < np; ++b) {
+                if (U & (1 << last[b])) continue;
+                const size_t nx = (b << M) | (size_t)(U | (1 << last[b]));
+                if (tab.get((int)a, (int)b) + val[k][nx] == want) {
+                    seq.push_back((int)b);
+                    U |= 1 << last[b];
+                    a = b;
+                    break;
+                }
+            }
+        }
+        return seq;
+    }
+    i64 optimum(int k) const { return val[k][(size_t)1 << (M - 1)]; }
+    i64 ties(int k) const { return cnt[k][(size_t)1 << (M - 1)]; }
 };
 
 }  // namespace
@@ -129,7 +259,7 @@ int fft_comm_volume(int M, const int64_t *dims, int64_t P, const int8_t *order, 
         if (!s) return fail(s);
         split = split || L[t].row_split();
     }
-    int8_t ident[kMaxDims];
+    int8_t ident[kMaxHostDims];
     for (int i = 0; i < M; ++i) ident[i] = (int8_t)i;
     s = make_layout(M, dims, P, ident, &L[M]);
     if (!s) return fail(s);
@@ -236,6 +366,7 @@ int fft_order_volumes(int M, const int64_t *dims, int64_t P, int ownership, int6
     if (!volumes) return fail(FFTRW_E_ARG, "volumes must not be null");
     Status s = check_dims(M, dims);
     if (!s) return fail(s);
+    if (M > 5) return fail(FFTRW_E_UNSUPPORTED, "one amount per order needs M <= 5 (use fft_order_search)");
     if (ownership != FFTRW_OWN_LITERAL && ownership != FFTRW_OWN_MATCHED)
         return fail(FFTRW_E_ARG, "unknown ownership reading");
     auto perms = all_perms(M);
@@ -247,6 +378,23 @@ int fft_order_volumes(int M, const int64_t *dims, int64_t P, int ownership, int6
         volumes[n] = v;
     });
     if (!tab.status) return fail(tab.status);
+    return FFTRW_OK;
+}
+
+int fft_transpose_volumes(int M, const int64_t *dims, int64_t P, int ownership, int64_t *table)
+{
+    g_last_error.clear();
+    if (!table) return fail(FFTRW_E_ARG, "table must not be null");
+    Status s = check_dims(M, dims);
+    if (!s) return fail(s);
+    if (ownership != FFTRW_OWN_LITERAL && ownership != FFTRW_OWN_MATCHED)
+        return fail(FFTRW_E_ARG, "unknown ownership reading");
+    auto perms = all_perms(M);
+    PairTable tab(M, dims, P, ownership, perms);
+    if (!tab.status) return fail(tab.status);
+    tab.fill(OrderSearch::pairs(M, perms));
+    if (!tab.status) return fail(tab.status);
+    std::memcpy(table, tab.vol.data(), sizeof(int64_t) * tab.vol.size());
     return FFTRW_OK;
 }
 
@@ -262,34 +410,29 @@ int fft_order_search(int M, const int64_t *dims, int64_t P, int ownership, int64
     auto perms = all_perms(M);
     PairTable tab(M, dims, P, ownership, perms);
     if (!tab.status) return fail(tab.status);
-    i64 bi = -1, bv = 0, nb = 0, wi = -1, wv = 0, nw = 0;
-    enumerate_orders(M, perms, [&](i64 n, const int *idx) {
-        i64 v = 0;
-        for (int t = 0; t + 1 < M; ++t) v += tab.get(idx[t], idx[t + 1]);
-        if (bi < 0 || v < bv) {
-            bi = n;
-            bv = v;
-            nb = 1;
-        } else if (v == bv) {
-            ++nb;
-        }
-        if (wi < 0 || v > wv) {
-            wi = n;
-            wv = v;
-            nw = 1;
-        } else if (v == wv) {
-            ++nw;
-        }
-    });
+    tab.fill(OrderSearch::pairs(M, perms));
     if (!tab.status) return fail(tab.status);
-    if (best_index) *best_index = bi;
-    if (best_volume) *best_volume = bv;
-    if (n_best) *n_best = nb;
-    if (worst_index) *worst_index = wi;
-    if (worst_volume) *worst_volume = wv;
-    if (n_worst) *n_worst = nw;
-    if (best_order) order_at(M, bi, best_order);
-    if (worst_order) order_at(M, wi, worst_order);
+    OrderSearch dp;
+    dp.run(M, perms, tab);
+    int8_t ord[kMaxHostDims * kMaxHostDims];
+    for (int k = 0; k < 2; ++k) {
+        const std::vector<int> seq = dp.walk(k, tab);
+        for (int t = 0; t < M; ++t) std::memcpy(ord + t * M, perms[seq[t]].data(), (size_t)M);
+        i64 idx = 0;
+        s = order_index(M, ord, &idx);
+        if (!s) return fail(s);
+        if (k == 0) {
+            if (best_index) *best_index = idx;
+            if (best_volume) *best_volume = dp.optimum(0);
+            if (n_best) *n_best = dp.ties(0);
+            if (best_order) std::memcpy(best_order, ord, (size_t)(M * M));
+        } else {
+            if (worst_index) *worst_index = idx;
+            if (worst_volume) *worst_volume = dp.optimum(1);
+            if (n_worst) *n_worst = dp.ties(1);
+            if (worst_order) std::memcpy(worst_order, ord, (size_t)(M * M));
+        }
+    }
     return FFTRW_OK;
 }
 

@@ -53,7 +53,7 @@ i64 box_overlap(const Box &a, const Box &b, int M)
 
 Status check_dims(int M, const i64 *dims)
 {
-    if (M < 2 || M > kMaxDims) return Status::err(-2, "M must be in [2, 5]");
+    if (M < 2 || M > kMaxHostDims) return Status::err(-2, "M must be in [2, 6]");
     if (!dims) return Status::err(-1, "dims is null");
     __int128 T = 1;
     for (int d = 0; d < M; ++d) {
@@ -67,7 +67,7 @@ Status check_dims(int M, const i64 *dims)
 Status check_perm(int M, const int8_t *perm)
 {
     if (!perm) return Status::err(-1, "permutation is null");
-    bool seen[kMaxDims] = {};
+    bool seen[kMaxHostDims] = {};
     for (int i = 0; i < M; ++i) {
         int a = perm[i];
         if (a < 0 || a >= M || seen[a]) return Status::err(-3, "not a permutation of the axes");
@@ -81,7 +81,7 @@ Status check_order(int M, const int8_t *order)
     if (!order) return Status::err(-1, "order is null");
     for (int i = 0; i < M; ++i)
         if (order[i] != i) return Status::err(-3, "the first decomposition must be the natural order");
-    bool last_used[kMaxDims] = {};
+    bool last_used[kMaxHostDims] = {};
     for (int t = 0; t < M; ++t) {
         Status s = check_perm(M, order + t * M);
         if (!s) return s;
@@ -228,11 +228,11 @@ i64 kept_literal(const Layout &a, const Layout &b)
 
 bool product_set_successor(int k, const i64 *l, const i64 *h, const i64 *n, i64 v, i64 *out)
 {
-    i64 w[kMaxDims];
+    i64 w[kMaxHostDims];
     w[k - 1] = 1;
     for (int i = k - 2; i >= 0; --i) w[i] = w[i + 1] * n[i + 1];
     if (v >= w[0] * n[0]) return false;
-    i64 d[kMaxDims];
+    i64 d[kMaxHostDims];
     i64 rem = v;
     for (int i = 0; i < k; ++i) {
         d[i] = rem / w[i];
@@ -474,12 +474,12 @@ i64 stage_choices(int M, int s)
 
 Status order_at(int M, i64 index, int8_t *order)
 {
-    if (M < 2 || M > kMaxDims) return Status::err(-2, "M must be in [2, 5]");
+    if (M < 2 || M > kMaxHostDims) return Status::err(-2, "M must be in [2, 6]");
     if (!order) return Status::err(-1, "order is null");
     i64 n = order_count(M);
     if (index < 0 || index >= n) return Status::err(-1, "order index out of range");
     auto perms = all_perms(M);
-    bool used[kMaxDims] = {};
+    bool used[kMaxHostDims] = {};
     for (int i = 0; i < M; ++i) order[i] = (int8_t)i;
     used[M - 1] = true;
     i64 rest = index;
@@ -506,7 +506,7 @@ Status order_index(int M, const int8_t *order, i64 *index)
     Status s = check_order(M, order);
     if (!s) return s;
     auto perms = all_perms(M);
-    bool used[kMaxDims] = {};
+    bool used[kMaxHostDims] = {};
     used[M - 1] = true;
     i64 idx = 0;
     for (int st = 1; st < M; ++st) {

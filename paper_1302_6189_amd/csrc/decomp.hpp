@@ -10,7 +10,8 @@
 namespace fftrw {
 
 using i64 = int64_t;
-constexpr int kMaxDims = 5;
+constexpr int kMaxDims = 5;      // plans and kernels: M = 2..5
+constexpr int kMaxHostDims = 6;  // host model (ranges, amounts, orders): M = 2..6
 
 struct Status {
     int code = 0;
@@ -24,10 +25,10 @@ struct Status {
 // split over P processes on the first k axes (Eq. (13)).
 struct Layout {
     int M = 0;
-    int perm[kMaxDims] = {};  // natural axis at each position
-    int pos[kMaxDims] = {};   // position of each natural axis
-    i64 pd[kMaxDims] = {};    // permuted sizes N'_i
-    i64 stride[kMaxDims] = {};// element stride of each *natural* axis in this layout
+    int perm[kMaxHostDims] = {};  // natural axis at each position
+    int pos[kMaxHostDims] = {};   // position of each natural axis
+    i64 pd[kMaxHostDims] = {};    // permuted sizes N'_i
+    i64 stride[kMaxHostDims] = {};// element stride of each *natural* axis in this layout
     int k = 0;                // level, 1-based
     i64 R = 0;                // rows over the first k axes
     i64 W = 0;                // points per row (product of the other axes)
@@ -45,8 +46,8 @@ struct Layout {
 
 // Axis-aligned box in natural coordinates, inclusive bounds.
 struct Box {
-    i64 lo[kMaxDims];
-    i64 hi[kMaxDims];
+    i64 lo[kMaxHostDims];
+    i64 hi[kMaxHostDims];
 };
 
 i64 box_volume(const Box &b, int M);
@@ -112,7 +113,7 @@ template <class F>
 void for_each_owner(const Layout &b, const Box &B, F &&f)
 {
     const int k = b.k;
-    i64 l[kMaxDims], h[kMaxDims], n[kMaxDims];
+    i64 l[kMaxHostDims], h[kMaxHostDims], n[kMaxHostDims];
     for (int i = 0; i < k; ++i) {
         int ax = b.perm[i];
         l[i] = B.lo[ax];

@@ -366,6 +366,7 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
     g_last_error.clear();
     if (!plan) return fail(FFTRW_E_ARG, "plan must not be null");
     *plan = nullptr;
+    if (M < 2 || M > kMaxDims) return fail(FFTRW_E_SIZE, "plans run M = 2..5");
     Status st = check_dims(M, dims);
     if (!st) return fail(st);
     if (P < 1) return fail(FFTRW_E_ARG, "P must be >= 1");

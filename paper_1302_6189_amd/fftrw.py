@@ -11,6 +11,7 @@ tensors (complex64 or complex128, contiguous) or raw integer pointers.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from typing import Sequence
 
@@ -55,6 +56,7 @@ _SIGNATURES = {
                                        _i64p, _i64p, _i64p]),
     "fft_rowsplit_volume": (ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, _i8p, _i64p, _i64p]),
     "fft_pair_counts": (ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, _i8p, _i8p, _i64p]),
+    "fft_transpose_volumes": (ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, _i64p]),
     "fft_order_count": (ctypes.c_int64, [ctypes.c_int]),
     "fft_order_at": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, _i8p]),
     "fft_order_index": (ctypes.c_int, [ctypes.c_int, _i8p, _i64p]),
@@ -196,6 +198,16 @@ def fft_pair_counts(dims, P, perm_a, perm_b):
     return C.reshape(int(P), int(P))
 
 
+def fft_transpose_volumes(dims, P, ownership=OWN_LITERAL):
+    """(M!, M!) int64 table of single-transpose amounts over the permutations
+    in lexicographic order; -1 where no order contains the pair."""
+    M = len(dims)
+    n = math.factorial(M)
+    out = np.zeros(n * n, dtype=np.int64)
+    _check(lib().fft_transpose_volumes(M, _dims(dims), int(P), int(ownership), out.ctypes.data_as(_i64p)))
+    return out.reshape(n, n)
+
+
 def fft_order_count(M):
     return int(lib().fft_order_count(int(M)))
 
@@ -227,7 +239,9 @@ def fft_order_search(dims, P, ownership=OWN_LITERAL):
 
 def fft_order_volumes(dims, P, ownership=OWN_LITERAL):
     M = len(dims)
-    out = np.zeros(fft_order_count(M), dtype=np.int64)
+    # past five axes the library refuses before writing (one entry per order
+    # would be 2.99e12 entries)
+    out = np.zeros(fft_order_count(M) if M <= 5 else 1, dtype=np.int64)
     _check(lib().fft_order_volumes(M, _dims(dims), int(P), int(ownership), out.ctypes.data_as(_i64p)))
     return out
 

@@ -200,6 +200,9 @@ def test_plan_errors_on_device(gpu_lib):
         fftrw.Plan((7, 8, 8), 2, "abc->acb->bca")
     assert e.value.code == fftrw.E_SIZE
     with pytest.raises(fftrw.FftrwError) as e:
+        fftrw.Plan((4,) * 6, 2, None)  # 6-D: host model only
+    assert e.value.code == fftrw.E_SIZE
+    with pytest.raises(fftrw.FftrwError) as e:
         fftrw.Plan((8, 8, 8), 513, "abc->acb->bca")  # more processes than points
     assert e.value.code == fftrw.E_ROWSPLIT
     with pytest.raises(fftrw.FftrwError) as e:

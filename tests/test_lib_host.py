@@ -165,8 +165,14 @@ def test_compare_models_match_oracle():
 
 def test_error_codes():
     with pytest.raises(fftrw.FftrwError) as e:
-        fftrw.fft_decomp((4,) * 6, 1, tuple(range(6)), 0)
+        fftrw.fft_decomp((4,) * 7, 1, tuple(range(7)), 0)
     assert e.value.code == fftrw.E_SIZE
+    # 6-D: ranges, amounts and the order search work; one amount per order
+    # (2,985,984,000,000 of them) does not
+    assert fftrw.fft_decomp((4,) * 6, 5, tuple(range(6)), 4)[0] == 2  # 4 < 5 <= 16
+    with pytest.raises(fftrw.FftrwError) as e:
+        fftrw.fft_order_volumes((2,) * 6, 2)
+    assert e.value.code == fftrw.E_UNSUPPORTED
     with pytest.raises(fftrw.FftrwError) as e:
         fftrw.fft_comm_volume((4, 4, 4), 4, "abc->acb->bcb")
     assert e.value.code == fftrw.E_ORDER

@@ -75,8 +75,18 @@ class Study:
         return int(hit[0])
 
 
+_STUDIES = {}
+
+
 def study(M, N, Ps, ownership="literal"):
-    """Total amount of every order of an N^M array for each N_p."""
+    """Total amount of every order of an N^M array for each N_p (memoised)."""
+    key = (M, N, tuple(Ps), ownership)
+    if key not in _STUDIES:
+        _STUDIES[key] = _study(M, N, Ps, ownership)
+    return _STUDIES[key]
+
+
+def _study(M, N, Ps, ownership):
     dims = (N,) * M
     ident = tuple(range(M))
     fn = decomp.pair_volume if ownership == "literal" else decomp.pair_volume_matched
@@ -177,6 +187,23 @@ def test_matched_always_best_five_d():
     best = _always_best(study(5, 4, [2 ** i for i in range(1, 9)], "matched"))
     assert len(best) == c["count5d_always_best"]
     assert set(_listed(5)) <= best
+
+
+def test_always_best_sets_have_the_balanced_forms():
+    # Section 3.3 describes the best orders by their shape: 1+2 or 2+1 for
+    # 3-D, 2+2 (neither 1+3 nor 3+1) for 4-D, 2+3 or 3+2 for 5-D.  Under the
+    # matched reading: the always-best 3-D set is exactly F(1+2) + F(2+1), the
+    # 4-D set exactly F(2+2); the 96 always-best 5-D orders are 48 of F(2+3)
+    # and 48 of F(3+2), and none has an unbalanced form.
+    fam = {(M, m1): set(orders.form_orders(M, m1)) for M in (3, 4, 5) for m1 in range(1, M)}
+    b3 = _always_best(study(3, 8, [2 ** i for i in range(1, 7)], "matched"))
+    assert b3 == fam[3, 1] | fam[3, 2]
+    b4 = _always_best(study(4, 8, [2 ** i for i in range(1, 10)], "matched"))
+    assert b4 == fam[4, 2] and not b4 & (fam[4, 1] | fam[4, 3])
+    b5 = _always_best(study(5, 4, [2 ** i for i in range(1, 9)], "matched"))
+    assert len(b5 & fam[5, 2]) == len(b5 & fam[5, 3]) == 48
+    assert b5 <= fam[5, 2] | fam[5, 3]
+    assert set(_listed(5)) <= fam[5, 2] and set(_listed(4)) == fam[4, 2]
 
 
 def test_literal_reading_does_not_give_the_listed_sets():
