@@ -151,9 +151,44 @@ __device__ __forceinline__ int64_t pair_base(const StagedTile &a, int p, int q)
 
 constexpr int kPairTab = 1024;  // dense (p, q) constants per pack tile
 constexpr int kTileItems = 16;  // tile elements per thread (tiles hold at most 4096)
+constexpr int kOwnHash = 512;   // distinct owners per side a pack tile numbers densely
+constexpr size_t kTileLdsMax = 64 * 1024;  // LDS of one pack or unpack tile
+
+// Number owner `key` densely: an open-addressing table (keys, -1 = free)
+// whose slots also hold the dense number, given by the thread that claims
+// the slot; `list` maps numbers back to owners.  Probing is bounded: past
+// kOwnHash steps the table is full and *overflow is set (the tile then keeps
+// the pair-by-pair path).
+__device__ __forceinline__ void own_insert(int *keys, int *num, int *list, int *count, int *overflow, int key)
+{
+    int h = (int)(((uint32_t)key * 2654435761u) >> 23) & (kOwnHash - 1);
+    for (int n = 0; n < kOwnHash; ++n, h = (h + 1) & (kOwnHash - 1)) {
+        int k = keys[h];
+        if (k == -1) {
+            k = atomicCAS(&keys[h], -1, key);
+            if (k == -1) {
+                const int i = atomicAdd(count, 1);
+                num[h] = i;
+                list[i] = key;
+                return;
+            }
+        }
+        if (k == key) return;
+    }
+    *overflow = 1;
+}
+
+// the dense number of an owner already inserted (table not overflowed)
+__device__ __forceinline__ int own_lookup(const int *keys, const int *num, int key)
+{
+    int h = (int)(((uint32_t)key * 2654435761u) >> 23) & (kOwnHash - 1);
+    for (int n = 0; n < kOwnHash; ++n, h = (h + 1) & (kOwnHash - 1))
+        if (keys[h] == key) return num[h];
+    return 0;
+}
 
 struct TileLds {
-    size_t tile, gbase, r0, wv, rb, sb, kp, pt, own_a, own_b, misc, total;
+    size_t tile, gbase, gc, r0, wv, rb, sb, kp, pt, own_a, own_b, hash, misc, total;
 };
 
 __host__ __device__ inline TileLds tile_lds(int lu, int lv, int lg, size_t esz, bool pack)
@@ -169,6 +204,7 @@ __host__ __device__ inline TileLds tile_lds(int lu, int lv, int lg, size_t esz, 
     };
     L.tile = take(G * SG * esz);
     L.gbase = take(G * 4);
+    L.gc = take(G * 3 * 4);
     L.r0 = take(G * TU * 4);
     L.wv = take(G * TU * 4);
     L.rb = pack ? 0 : take(G * TU * 4);
@@ -177,6 +213,7 @@ __host__ __device__ inline TileLds tile_lds(int lu, int lv, int lg, size_t esz, 
     L.pt = pack ? take(kPairTab * 4) : 0;
     L.own_a = take(G * TV * 4);
     L.own_b = take(G * TU * 4);
+    L.hash = pack ? take(6 * kOwnHash * 4) : 0;  // keys, numbers, lists for p and q
     L.misc = take(16);
     L.total = o;
     return L;
@@ -246,6 +283,7 @@ __global__ void __launch_bounds__(kThreads)
     const TileLds L = tile_lds(lu, lv, lg, sizeof(C), PACK);
     C *tile = reinterpret_cast<C *>(smem + L.tile);
     int *gbase = reinterpret_cast<int *>(smem + L.gbase);
+    int *gc = reinterpret_cast<int *>(smem + L.gc);  // batch coordinates of each slice
     int *r0 = reinterpret_cast<int *>(smem + L.r0);
     int *wv = reinterpret_cast<int *>(smem + L.wv);
     int *rb = reinterpret_cast<int *>(smem + L.rb);
@@ -254,21 +292,28 @@ __global__ void __launch_bounds__(kThreads)
     int *pt = reinterpret_cast<int *>(smem + L.pt);
     int *own_a = reinterpret_cast<int *>(smem + L.own_a);
     int *own_b = reinterpret_cast<int *>(smem + L.own_b);
-    int *mm = reinterpret_cast<int *>(smem + L.misc);  // pmin, pmax, qmin, qmax
+    int *mm = reinterpret_cast<int *>(smem + L.misc);  // distinct p, distinct q, overflow
+    int *hk = reinterpret_cast<int *>(smem + L.hash);  // [side][kOwnHash] keys, numbers, lists
+    int *hn = hk + 2 * kOwnHash;
+    int *hl = hn + 2 * kOwnHash;
 
     // owners, slice bases, cleared accumulators
     if (PACK && threadIdx.x == 0) {
-        mm[0] = INT_MAX;
-        mm[1] = -1;
-        mm[2] = INT_MAX;
-        mm[3] = -1;
+        mm[0] = 0;
+        mm[1] = 0;
+        mm[2] = 0;
     }
-    tile_owners(d, g0, ng, u0, nu, v0, nv, own_a, own_b);
+    if (PACK)
+        for (int i = threadIdx.x; i < 2 * kOwnHash; i += kThreads) hk[i] = -1;
+    // each slice's coordinates once (64-bit divisions), then owners from them
     for (int g = threadIdx.x; g < ng; g += kThreads) {
-        int c[3];
+        int c[3] = {0, 0, 0};
         int64_t ab, bb;
         slice_coords(d, g0 + g, c, &ab, &bb);
         gbase[g] = (int)(PACK ? ab : bb);
+        gc[3 * g] = c[0];
+        gc[3 * g + 1] = c[1];
+        gc[3 * g + 2] = c[2];
     }
     for (int i = threadIdx.x; i < G * TU; i += kThreads) {
         r0[i] = 0;
@@ -276,6 +321,30 @@ __global__ void __launch_bounds__(kThreads)
     }
     if (PACK)
         for (int i = threadIdx.x; i < kPairTab; i += kThreads) pt[i] = 0;
+    __syncthreads();
+    {
+        // below level M, A's leading axes are batch axes and v, B's are batch
+        // axes and u (the staged path refuses level M)
+        const bool narrow = d.owner32 != 0;
+        for (int i = threadIdx.x; i < ng * nv; i += kThreads) {
+            const int g = i / nv, iv = i - g * nv;
+            int64_t r = 0;
+            for (int j = 0; j < d.ka; ++j) {
+                const int src = d.srca[j];
+                r += (src == 3 ? v0 + iv : (int64_t)gc[3 * g + src]) * d.wa[j];
+            }
+            own_a[g * TV + iv] = (int)owner_of_row(r, d.P, d.Ra, narrow);
+        }
+        for (int i = threadIdx.x; i < ng * nu; i += kThreads) {
+            const int g = i / nu, iu = i - g * nu;
+            int64_t r = 0;
+            for (int j = 0; j < d.kb; ++j) {
+                const int src = d.srcb[j];
+                r += (src == 4 ? u0 + iu : (int64_t)gc[3 * g + src]) * d.wb[j];
+            }
+            own_b[g * TU + iu] = (int)owner_of_row(r, d.P, d.Rb, narrow);
+        }
+    }
     __syncthreads();
 
     // ranks per (slice, u): one task per (entry, box of q's range); unpack also
@@ -294,9 +363,7 @@ __global__ void __launch_bounds__(kThreads)
             kp[k] = (int)R.kept;
             continue;
         }
-        int bc[3];
-        int64_t ab, bb;
-        slice_coords(d, g0 + g, bc, &ab, &bb);
+        const int *bc = gc + 3 * g;
         int c[kMaxDims];
 #pragma unroll
         for (int m = 0; m < kMaxDims; ++m) {
@@ -313,41 +380,24 @@ __global__ void __launch_bounds__(kThreads)
         lds_add(&wv[k], rn - ra);
     }
     if (PACK) {
-        int lo = INT_MAX, hi = -1;
-        for (int i = threadIdx.x; i < ng * nv; i += kThreads) {
-            const int p = own_a[(i / nv) * TV + i % nv];
-            lo = min(lo, p);
-            hi = max(hi, p);
-        }
-        if (hi >= 0) {
-            atomicMin(&mm[0], lo);
-            atomicMax(&mm[1], hi);
-        }
-        lo = INT_MAX;
-        hi = -1;
-        for (int i = threadIdx.x; i < ng * nu; i += kThreads) {
-            const int q = own_b[(i / nu) * TU + i % nu];
-            lo = min(lo, q);
-            hi = max(hi, q);
-        }
-        if (hi >= 0) {
-            atomicMin(&mm[2], lo);
-            atomicMax(&mm[3], hi);
-        }
+        // number the tile's distinct owners densely, p (A) and q (B) apart
+        for (int i = threadIdx.x; i < ng * nv; i += kThreads)
+            own_insert(hk, hn, hl, &mm[0], &mm[2], own_a[(i / nv) * TV + i % nv]);
+        for (int i = threadIdx.x; i < ng * nu; i += kThreads)
+            own_insert(hk + kOwnHash, hn + kOwnHash, hl + kOwnHash, &mm[1], &mm[2], own_b[(i / nu) * TU + i % nu]);
     }
     __syncthreads();
 
-    // pack: D(p, q) for every (p, q) in the tile's owner spans, one task per
-    // (pair, box) plus one for xs_p
-    const int pmin = PACK ? mm[0] : 0, qmin = PACK ? mm[2] : 0;
-    const int nq = PACK ? mm[3] - qmin + 1 : 0;
-    const bool dense = PACK && (int64_t)(mm[1] - pmin + 1) * nq <= kPairTab;
+    // pack: D(p, q) for every pair of the tile's distinct owners, one task per
+    // (pair, box) plus one for xs_p; the owner tables then hold dense numbers
+    const int np = PACK ? mm[0] : 0, nq = PACK ? mm[1] : 0;
+    const bool dense = PACK && mm[2] == 0 && np * nq <= kPairTab;
     if (PACK && dense) {
         const int per = a.nbp + a.nbq + 1;
-        const int n = (mm[1] - pmin + 1) * nq * per;
+        const int n = np * nq * per;
         for (int i = threadIdx.x; i < n; i += kThreads) {
             const int e = i / per, j = i - e * per;
-            const int p = pmin + e / nq, q = qmin + e % nq;
+            const int p = hl[e / nq], q = hl[kOwnHash + e % nq];
             const SendInfo &S = a.send[p];
             const RecvInfo &R = a.recv[q];
             int64_t v;
@@ -361,6 +411,14 @@ __global__ void __launch_bounds__(kThreads)
                 v = S.xs;
             }
             lds_add(&pt[e], v);
+        }
+        for (int i = threadIdx.x; i < ng * nv; i += kThreads) {
+            int &o = own_a[(i / nv) * TV + i % nv];
+            o = own_lookup(hk, hn, o);
+        }
+        for (int i = threadIdx.x; i < ng * nu; i += kThreads) {
+            int &o = own_b[(i / nu) * TU + i % nu];
+            o = own_lookup(hk + kOwnHash, hn + kOwnHash, o);
         }
         __syncthreads();
     }
@@ -402,9 +460,7 @@ __global__ void __launch_bounds__(kThreads)
         if (dense) {
             tile_pass<LW>(lu, lv, lg, nu, nv, ng, [&](int, int g, int iv, int iu) {
                 const int k = g * TU + iu;
-                const int p = own_a[g * TV + iv];
-                const int q = own_b[k];
-                const int off = pt[(p - pmin) * nq + (q - qmin)] + r0[k] + iv * wv[k];
+                const int off = pt[own_a[g * TV + iv] * nq + own_b[k]] + r0[k] + iv * wv[k];
                 if ((uint32_t)off < (uint32_t)a.T) xst(dst + off, tile[g * SG + iv * SV + iu]);
             });
         } else {
@@ -634,8 +690,15 @@ StagedTileCfg make_tile(const fft_plan_impl *pl, int t, int seg_axis, bool pack)
         }
     }
     // extents: the read and write axes first, then fill up to the budget;
-    // each axis at most 256 (one lane pass), slices x u at most 512 (tables)
-    const int budget = pl->esz == 8 ? 11 : 10;
+    // each axis at most 256 (one lane pass), slices x u at most 512 (tables).
+    // 4096 values per tile (2048 in FP64) spread the per-tile rank and pair
+    // set-up over more points; tiles that run along the slices keep 2048
+    // (1024): their gathers need the extra resident groups more (measured).
+    const int f = seg_axis == u ? 0 : (seg_axis == v ? 1 : 2);
+    c.lane_r = pack ? 0 : f;
+    c.lane_w = pack ? f : 1;
+    const int ra = c.lane_r, wa = c.lane_w;
+    const int budget = (pl->esz == 8 ? 12 : 11) - (ra == 2 || wa == 2 ? 1 : 0);
     const int cap[3] = {std::min(8, ilog2ceil(d.Nu)), std::min(8, ilog2ceil(d.Nv)),
                         nb ? std::min(8, ilog2ceil(d.bsize[0])) : 0};
     int l[3] = {0, 0, 0};
@@ -646,10 +709,6 @@ StagedTileCfg make_tile(const fft_plan_impl *pl, int t, int seg_axis, bool pack)
     };
     auto want = [&](int ax, int lg2) { l[ax] = std::min(cap[ax], std::max(l[ax], std::min(lg2, l[ax] + room(ax)))); };
     auto fill = [&](int ax) { l[ax] = std::min(cap[ax], l[ax] + room(ax)); };
-    const int f = seg_axis == u ? 0 : (seg_axis == v ? 1 : 2);
-    c.lane_r = pack ? 0 : f;
-    c.lane_w = pack ? f : 1;
-    const int ra = c.lane_r, wa = c.lane_w;
     if (ra == wa) {
         want(ra, 6);
     } else if (ra != 2 && wa != 2) {
@@ -662,6 +721,17 @@ StagedTileCfg make_tile(const fft_plan_impl *pl, int t, int seg_axis, bool pack)
     fill(1);
     fill(0);
     fill(2);
+    // a tile that is narrow along u pads every u-line: keep its LDS within 64 KB
+    // by shrinking the largest axis that is not a lane axis (else the largest)
+    while (tile_lds(l[0], l[1], l[2], pl->esz, pack).total > kTileLdsMax) {
+        int ax = -1;
+        for (int x = 0; x < 3; ++x)
+            if (x != ra && x != wa && l[x] > 0 && (ax < 0 || l[x] > l[ax])) ax = x;
+        if (ax < 0)
+            for (int x = 0; x < 3; ++x)
+                if (l[x] > 0 && (ax < 0 || l[x] > l[ax])) ax = x;
+        --l[ax];
+    }
     c.lu = l[0];
     c.lv = l[1];
     c.lg = l[2];

@@ -79,41 +79,6 @@ __device__ __forceinline__ void slice_coords(const XposeDesc &d, int64_t s, int 
     *bb = b;
 }
 
-// Owner vectors of one tile: A's over (slice, v) into own_a[g * TV + iv], B's
-// over (slice, u) into own_b[g * TU + iu] (slices g0 .. g0 + ng - 1).  Below
-// level M only (the staged transposes, which need whole rows).
-__device__ __forceinline__ void tile_owners(const XposeDesc &d, int64_t g0, int ng, int64_t u0, int nu, int64_t v0,
-                                            int nv, int *own_a, int *own_b)
-{
-    const bool narrow = d.owner32 != 0;
-    for (int i = threadIdx.x; i < ng * nv; i += kThreads) {
-        const int g = i / nv, iv = i - g * nv;
-        int c[3];
-        int64_t ab, bb;
-        slice_coords(d, g0 + g, c, &ab, &bb);
-        int64_t r = 0;
-        for (int j = 0; j < d.ka; ++j) {
-            const int src = d.srca[j];
-            r += (src == 3 ? v0 + iv : (int64_t)c[src]) * d.wa[j];
-        }
-        int64_t o = owner_of_row(r, d.P, d.Ra, narrow);
-        if (d.mu) o = d.mu[o];
-        own_a[g * d.TV + iv] = (int)o;
-    }
-    for (int i = threadIdx.x; i < ng * nu; i += kThreads) {
-        const int g = i / nu, iu = i - g * nu;
-        int c[3];
-        int64_t ab, bb;
-        slice_coords(d, g0 + g, c, &ab, &bb);
-        int64_t r = 0;
-        for (int j = 0; j < d.kb; ++j) {
-            const int src = d.srcb[j];
-            r += (src == 4 ? u0 + iu : (int64_t)c[src]) * d.wb[j];
-        }
-        own_b[g * d.TU + iu] = (int)owner_of_row(r, d.P, d.Rb, narrow);
-    }
-}
-
 // Points of the row (batch coordinates c, v) with u in [u0, u0 + nu) that keep
 // their owner.  Both row indices are affine in u: B's grows with u when u is
 // one of B's leading axes, A's only at level M.  Owners are monotone in the
