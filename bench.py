@@ -266,8 +266,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: the virtual processes of the "
-                                   "decomposition live on a single device; run with --gpus 1"}))
+        print(json.dumps({"error": "fftrw runs on one GPU: the virtual processes of the decomposition "
+                                   "share a single device; run with --gpus 1"}))
         sys.exit(2)
 
     import numpy as np
