@@ -203,6 +203,9 @@ def test_plan_errors_on_device(gpu_lib):
         fftrw.Plan((4,) * 6, 2, None)  # 6-D: host model only
     assert e.value.code == fftrw.E_SIZE
     with pytest.raises(fftrw.FftrwError) as e:
+        fftrw.Plan((4096, 4096, 4096), 8, None, dtype=fftrw.C128)  # a 1.1 TB workspace
+    assert e.value.code == fftrw.E_NOMEM
+    with pytest.raises(fftrw.FftrwError) as e:
         fftrw.Plan((8, 8, 8), 513, "abc->acb->bca")  # more processes than points
     assert e.value.code == fftrw.E_ROWSPLIT
     with pytest.raises(fftrw.FftrwError) as e:
