@@ -59,19 +59,45 @@ __device__ __forceinline__ void stockham_pass(C *row, int N, int Ns, int lanes, 
     __syncthreads();
 }
 
+// Copies cnt values into LDS; each thread issues up to kLoadBatch loads before
+// storing any of them, so its share of the block is in flight at once.
+constexpr int kLoadBatch = 8;
+
+template <typename T>
+__device__ __forceinline__ void load_batched(T *lds, const T *__restrict__ src, int n)
+{
+    for (int e0 = threadIdx.x; e0 < n; e0 += kThreads * kLoadBatch) {
+        T t[kLoadBatch];
+#pragma unroll
+        for (int j = 0; j < kLoadBatch; ++j) {
+            const int e = e0 + j * kThreads;
+            if (e < n) t[j] = src[e];
+        }
+#pragma unroll
+        for (int j = 0; j < kLoadBatch; ++j) {
+            const int e = e0 + j * kThreads;
+            if (e < n) lds[e] = t[j];
+        }
+    }
+}
+
 template <typename C>
 __device__ __forceinline__ void load_block(C *lds, const C *__restrict__ src, int cnt)
 {
+    // native vector types keep the batch in registers
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    typedef double d2v __attribute__((ext_vector_type(2)));
     if constexpr (sizeof(C) == 8) {
         // two complex floats per 16-byte access when the block is even-sized
         if ((cnt & 1) == 0 && (((uintptr_t)src) & 15) == 0) {
-            const float4 *s4 = reinterpret_cast<const float4 *>(src);
-            float4 *l4 = reinterpret_cast<float4 *>(lds);
-            for (int e = threadIdx.x; e < (cnt >> 1); e += kThreads) l4[e] = s4[e];
+            load_batched(reinterpret_cast<f4v *>(lds), reinterpret_cast<const f4v *>(src), cnt >> 1);
             return;
         }
+        load_batched(reinterpret_cast<f2v *>(lds), reinterpret_cast<const f2v *>(src), cnt);
+    } else {
+        load_batched(reinterpret_cast<d2v *>(lds), reinterpret_cast<const d2v *>(src), cnt);
     }
-    for (int e = threadIdx.x; e < cnt; e += kThreads) lds[e] = src[e];
 }
 
 template <typename C>

@@ -22,6 +22,8 @@
 
 namespace fftrw {
 
+constexpr int kUnitItems = 16;  // loads in flight per thread while a unit is staged
+
 // Shape of a fused unit for rows of length N: RW rows per slice (a power of
 // two covering the v extent when it can) and G slices, so that a unit holds at
 // most `budget` values (4096 complex64, 2048 complex128) and every row keeps at
@@ -69,25 +71,40 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
     __syncthreads();
 
     // rows (slice g0 + gi, v0 + r), rho = gi nv + r: N contiguous values each;
-    // element e = rho N + c, stepped by kThreads without divisions
+    // element e = rho N + c, stepped by kThreads without divisions.  Up to
+    // kUnitItems loads are issued before any of them is stored to LDS, so a
+    // thread keeps its whole share in flight (a unit holds at most 16 values
+    // per thread).
     {
         const int drho = kThreads / N, dc = kThreads - drho * N;
         int rho = threadIdx.x / N, c = threadIdx.x - rho * N;
         int gi = rho / nv, r = rho - gi * nv;
         const int drg = drho / nv, drr = drho - drg * nv;
         while (gi < ng) {
-            lds[(gi * rw + r) * S + c] = xld(in + abase[gi] + (v0 + r) * d.a_sv + c);
-            c += dc;
-            gi += drg;
-            r += drr;
-            if (c >= N) {
-                c -= N;
-                ++r;
+            C val[kUnitItems];
+            int at[kUnitItems];
+#pragma unroll
+            for (int j = 0; j < kUnitItems; ++j) {
+                at[j] = -1;
+                if (gi < ng) {
+                    at[j] = (gi * rw + r) * S + c;
+                    val[j] = xld(in + abase[gi] + (v0 + r) * d.a_sv + c);
+                    c += dc;
+                    gi += drg;
+                    r += drr;
+                    if (c >= N) {
+                        c -= N;
+                        ++r;
+                    }
+                    while (r >= nv) {
+                        r -= nv;
+                        ++gi;
+                    }
+                }
             }
-            while (r >= nv) {
-                r -= nv;
-                ++gi;
-            }
+#pragma unroll
+            for (int j = 0; j < kUnitItems; ++j)
+                if (at[j] >= 0) lds[at[j]] = val[j];
         }
     }
     __syncthreads();
