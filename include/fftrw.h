@@ -33,6 +33,10 @@
  * - Pointers named `in`/`out` and the `stream` argument are HIP device
  *   pointers and a hipStream_t (NULL = the default stream).  Host pointers are
  *   named otherwise and are only read/written during the call.
+ * - Diagnostics: the environment variable FFTRW_LOG (read once per process)
+ *   selects lines on stderr, each starting "fftrw: ": 1 = every error and
+ *   every plan or batch created (order, kernels, workspace), 2 = also each
+ *   order search, 3 = also each execution.  Unset or 0: silent.
  */
 #ifndef FFTRW_H
 #define FFTRW_H

@@ -3,6 +3,9 @@
 // models.  No HIP calls here, so these work on a machine without a GPU.
 #include <algorithm>
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -19,9 +22,30 @@ namespace fftrw {
 
 thread_local std::string g_last_error;
 
+int log_level()
+{
+    static const int level = [] {
+        const char *v = std::getenv("FFTRW_LOG");
+        return v ? std::max(0, std::min(3, std::atoi(v))) : 0;
+    }();
+    return level;
+}
+
+void log_line(int level, const char *fmt, ...)
+{
+    if (log_level() < level) return;
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "fftrw: %s\n", buf);
+}
+
 int fail(int code, const std::string &msg)
 {
     g_last_error = msg;
+    log_line(1, "error %d: %s", code, msg.c_str());
     return code;
 }
 
@@ -414,6 +438,9 @@ int fft_order_search(int M, const int64_t *dims, int64_t P, int ownership, int64
     if (!tab.status) return fail(tab.status);
     OrderSearch dp;
     dp.run(M, perms, tab);
+    log_line(2, "order search M=%d P=%lld ownership=%d: least %lld (%lld orders), largest %lld (%lld orders)", M,
+             (long long)P, ownership, (long long)dp.optimum(0), (long long)dp.ties(0), (long long)dp.optimum(1),
+             (long long)dp.ties(1));
     int8_t ord[kMaxHostDims * kMaxHostDims];
     for (int k = 0; k < 2; ++k) {
         const std::vector<int> seq = dp.walk(k, tab);

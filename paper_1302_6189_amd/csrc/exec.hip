@@ -526,6 +526,18 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
         free_plan(pl);
         return fail(FFTRW_E_DEVICE, "device error during plan creation");
     }
+    if (log_level() >= 1) {
+        char text[256];
+        (void)fft_plan_describe(pl, nullptr, text, sizeof(text));
+        std::string dd, oo;
+        for (int i = 0; i < M; ++i) dd += (i ? "x" : "") + std::to_string(dims[i]);
+        for (int t = 0; t < M; ++t) {
+            if (t) oo += "->";
+            for (int i = 0; i < M; ++i) oo += (char)('a' + pl->order[t * M + i]);
+        }
+        log_line(1, "plan %s P=%lld order %s kernels %s flags 0x%x workspace %zu bytes", dd.c_str(), (long long)P,
+                 oo.c_str(), text, flags, pl->dev_bytes);
+    }
     *plan = pl;
     return FFTRW_OK;
 }
@@ -548,6 +560,7 @@ int fft_exec_fwd(fft_plan_t plan, const void *in, void *out, void *stream)
 {
     g_last_error.clear();
     if (!plan || !in || !out) return fail(FFTRW_E_ARG, "null plan or buffer");
+    log_line(3, "exec forward plan %p in %p out %p stream %p", (void *)plan, in, out, stream);
     return run_pipeline(plan, in, out, (hipStream_t)stream, -1);
 }
 
@@ -555,6 +568,7 @@ int fft_exec_inv(fft_plan_t plan, const void *in, void *out, void *stream)
 {
     g_last_error.clear();
     if (!plan || !in || !out) return fail(FFTRW_E_ARG, "null plan or buffer");
+    log_line(3, "exec inverse plan %p in %p out %p stream %p", (void *)plan, in, out, stream);
     return run_pipeline(plan, in, out, (hipStream_t)stream, +1);
 }
 

@@ -310,3 +310,19 @@ def test_matched_ownership_device_counts(gpu_lib, dims, P, oidx, fused):
     assert moved == analytic
     ref = dft.fftn_direct(x, orders.fft_axis_sequence(order))
     assert dft.rel_l2(to_host(yd), ref) < 1e-5
+
+
+def test_plan_log_line(gpu_lib):
+    # FFTRW_LOG=1: one line per plan created, naming its order and kernels
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_1302_6189_amd import fftrw\n"
+            "p = fftrw.Plan((8, 8, 8), 4, 'abc->acb->bca', flags=fftrw.FLAG_FUSED_FFT)\n")
+    env = dict(os.environ, FFTRW_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, stdout=subprocess.PIPE,
+                       stderr=subprocess.PIPE, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    lines = [l for l in r.stderr.splitlines() if l.startswith("fftrw: plan ")]
+    assert len(lines) == 1 and "8x8x8 P=4 order abc->acb->bca kernels" in lines[0], r.stderr
