@@ -164,3 +164,19 @@ def test_in_place_needs_the_separate_schedule(gpu_lib):
         order = fftrw.fft_order_search(d, P)["best_order"]
         ref = dft.fftn_direct(xs[i], orders.fft_axis_sequence(order))
         assert dft.rel_l2(to_host(ins[i]), ref) < 1e-5
+
+
+@pytest.mark.parametrize("flags", [0, fftrw.FLAG_BATCH_NO_FUSE])
+def test_long_rows_in_a_batch(gpu_lib, flags):
+    # a row longer than 2047 points switches the batch to 16 values per lane
+    items = [((2560, 3, 2), 3), ((12, 15, 16), 5), ((4096, 2, 2), 2)]
+    xs = [inputs.uniform(d, 80 + i, np.complex64) for i, (d, _) in enumerate(items)]
+    b = fftrw.Batch(items, flags=flags | fftrw.FLAG_COUNT_MOVED)
+    ins, outs = _run(b, xs)
+    st = b.stats()
+    assert st["error"] == 0
+    for i, (dims, P) in enumerate(items):
+        order = fftrw.fft_order_search(dims, P)["best_order"]
+        ref = dft.fftn_direct(xs[i], orders.fft_axis_sequence(order))
+        assert dft.rel_l2(to_host(outs[i]), ref) < 1e-5, (i, dims)
+        assert st["moved"][i] == st["analytic"][i]
