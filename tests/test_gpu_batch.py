@@ -81,7 +81,7 @@ def test_batch_matches_per_item_plans(gpu_lib):
         assert st["moved"][i] == st["analytic"][i]
 
 
-def test_config5_full_batch(gpu_lib):
+def test_full_256_item_batch(gpu_lib):
     items = inputs.batch_items(256, seed=5)
     xs = [inputs.uniform(d, 1000 + i, np.complex64) for i, (d, _) in enumerate(items)]
     b = fftrw.Batch(items, flags=fftrw.FLAG_COUNT_MOVED)

@@ -96,7 +96,7 @@ def test_transpose_bit_exact_and_counted(gpu_lib, dims, P, order, dtype, staged)
 
 @pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
 @pytest.mark.parametrize("oidx", range(8))
-def test_config1_all_orders(gpu_lib, oidx, dtype):
+def test_32cube_all_orders(gpu_lib, oidx, dtype):
     # 32^3, P = 4, every 3-D order; the oracle consumes exactly the GPU's input
     dims, P = (32, 32, 32), 4
     order = list(orders.all_orders(3))[oidx]
@@ -145,7 +145,7 @@ def test_in_place_and_leave_permuted(gpu_lib, staged):
                                          ((32, 32, 32, 32, 16), 48, 0), ((32, 32, 32, 32, 16), 256, 3333333),
                                          ((32, 32, 32, 32, 16), 1000, 7962623)])
 @pytest.mark.parametrize("staged", [False, True])
-def test_config3_orders(gpu_lib, dims, P, oidx, staged):
+def test_64pow4_and_32pow4x16_orders(gpu_lib, dims, P, oidx, staged):
     M = len(dims)
     order = fftrw.fft_order_at(M, oidx)
     extra = fftrw.FLAG_STAGED if staged else 0
@@ -167,7 +167,7 @@ def test_config3_orders(gpu_lib, dims, P, oidx, staged):
 
 
 @pytest.mark.parametrize("P,which", [(8, "best"), (4096, "best"), (4096, "worst"), (512, "worst")])
-def test_config2_full_size_sampled(gpu_lib, P, which):
+def test_512cube_full_size_sampled(gpu_lib, P, which):
     # 512^3 complex64 at full size: points of Eq. (2) computed one by one in
     # FP64, Parseval over the whole output, exact device counts
     dims = (512, 512, 512)

@@ -51,7 +51,7 @@ def cube256():
 
 @pytest.mark.parametrize("name", list(PRECS))
 @pytest.mark.parametrize("kind", ["uniform", "log_uniform"])
-def test_config4_256cube(gpu_lib, cube256, name, kind):
+def test_256cube_precision_forms(gpu_lib, cube256, name, kind):
     prec, tol = PRECS[name]
     order, data = cube256
     x, ref = data[kind]

@@ -138,7 +138,7 @@ def test_order_search_matches_brute_force(dims, P):
     assert list(fftrw.fft_order_volumes(dims, P)) == vols
 
 
-def test_config_level_amounts():
+def test_512cube_level_amounts():
     # 512^3: slabs for N_p <= 512 (one leading-axis change: T (1 - 1/N_p));
     # N_p = 4096 = 8 N: closed forms of the 2-D regime (canonical indices)
     N, T = 512, 512 ** 3

@@ -165,7 +165,7 @@ def test_matched_never_exceeds_literal():
                 assert mat == prod(dims) - best
 
 
-def test_config1_volumes():
+def test_32cube_four_process_volumes():
     # 32^3, N_p = 4: slabs of 8 a-planes; a leading-axis change moves 3/4 of T
     dims, P = (32, 32, 32), 4
     O = list(orders.all_orders(3))
