@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "cplx.hpp"
 #include "kernels.hpp"
@@ -234,6 +235,7 @@ __global__ void __launch_bounds__(kThreads)
 // operands (FP64 sin/cos) are built once per work-group.  Owner changes are
 // counted per row (tile_moved).
 constexpr int kMfmaRows = 16;
+constexpr int kMaxDevices = 64;  // devices whose resident grid size is cached
 
 template <int PREC, int DIR>
 __global__ void __launch_bounds__(kThreads)
@@ -390,17 +392,20 @@ hipError_t launch_fft256_mfma_xpose(int precision, int dir, const void *tw256, c
 {
     const int64_t nunits = ((d.Nv + kMfmaRows - 1) / kMfmaRows) * d.nslices;
     if (nunits <= 0) return hipSuccess;
-    // a resident grid (work-groups walk the units)
-    static int resident = 0;
+    // a resident grid (work-groups walk the units), sized once per device
+    static std::atomic<int> resident_of[kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+    int resident = dev < kMaxDevices ? resident_of[dev].load(std::memory_order_relaxed) : 0;
     if (resident == 0) {
-        int dev = 0, ncu = 0, per_cu = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        int ncu = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fft256_mfma_xpose_kernel<kPrecF16, -1>, kThreads,
                                                          0) != hipSuccess ||
             ncu < 1 || per_cu < 1)
             return hipErrorInvalidDeviceFunction;
         resident = ncu * per_cu;
+        if (dev < kMaxDevices) resident_of[dev].store(resident, std::memory_order_relaxed);
     }
     const int ds = scale != 1.0;
     dim3 grid((unsigned)std::min<int64_t>(nunits, resident)), block(kThreads);
