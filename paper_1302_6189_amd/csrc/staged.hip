@@ -501,6 +501,7 @@ __global__ void __launch_bounds__(kThreads)
     exchange_kernel(const C *__restrict__ send, C *__restrict__ recv, ExchangeArgs a)
 {
     __shared__ int64_t s_xoff[kChunkSegsLds];
+    __shared__ int64_t s_src[kChunkSegsLds], s_dst[kChunkSegsLds];  // segment offsets minus xoff
     __shared__ int copied_wg;
     const int64_t x0 = (int64_t)blockIdx.x * kChunk;
     const int64_t x1 = min<int64_t>(x0 + kChunk, a.total) - 1;
@@ -528,11 +529,17 @@ __global__ void __launch_bounds__(kThreads)
             }
         }
     } else {
-        // several segments: their starts in LDS when few enough
+        // several segments: their descriptors in LDS when few enough, so a
+        // point's copy needs one global load (its value), not two
         const int nseg = (int)(ls - fs + 1);
         const bool in_lds = nseg <= kChunkSegsLds;
         if (in_lds)
-            for (int i = threadIdx.x; i < nseg; i += kThreads) s_xoff[i] = a.segs[fs + i].xoff;
+            for (int i = threadIdx.x; i < nseg; i += kThreads) {
+                const SegCopy S = a.segs[fs + i];
+                s_xoff[i] = S.xoff;
+                s_src[i] = S.src - S.xoff;
+                s_dst[i] = S.dst - S.xoff;
+            }
         __syncthreads();
         int64_t to[kChunkItems];
 #pragma unroll
@@ -541,15 +548,17 @@ __global__ void __launch_bounds__(kThreads)
             to[j] = -1;
             if (i < n) {
                 const int64_t x = x0 + i;
-                int64_t si;
-                if (in_lds)
-                    si = fs + upper_index([&](int64_t m) { return s_xoff[m]; }, 0, nseg - 1, x);
-                else
-                    si = upper_index([&](int64_t m) { return a.segs[m].xoff; }, fs, ls, x);
-                const SegCopy &S = a.segs[si];
-                const int64_t o = x - S.xoff;
-                to[j] = S.dst + o;
-                v[j] = xld(send + S.src + o);
+                if (in_lds) {
+                    const int64_t m = upper_index([&](int64_t q) { return s_xoff[q]; }, 0, nseg - 1, x);
+                    to[j] = s_dst[m] + x;
+                    v[j] = xld(send + s_src[m] + x);
+                } else {
+                    const int64_t si = upper_index([&](int64_t q) { return a.segs[q].xoff; }, fs, ls, x);
+                    const SegCopy &S = a.segs[si];
+                    const int64_t o = x - S.xoff;
+                    to[j] = S.dst + o;
+                    v[j] = xld(send + S.src + o);
+                }
             }
         }
 #pragma unroll
