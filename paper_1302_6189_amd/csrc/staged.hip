@@ -725,7 +725,7 @@ StagedTileCfg make_tile(const fft_plan_impl *pl, int t, int seg_axis, bool pack)
         want(wa, budget / 2);
     } else {
         want(ra == 2 ? wa : ra, 4);
-        want(2, 5);
+        want(2, 4);  // 16 slices: 128-byte runs, half the rank tasks of 32 (measured best)
     }
     fill(1);
     fill(0);
