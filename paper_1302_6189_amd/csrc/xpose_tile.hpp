@@ -102,12 +102,21 @@ __device__ __forceinline__ int64_t row_keep(const XposeDesc &d, const int *c, in
         else
             rb0 += (src == 3 ? v : (int64_t)c[src]) * d.wb[j];
     }
-    // ceil(x / w) for w > 0 (integer division truncates towards zero)
-    auto cdiv = [](int64_t x, int64_t w) { return x >= 0 ? (x + w - 1) / w : x / w; };
+    // floor(x / y) for x >= 0, y > 0, and ceil(x / w) for w > 0.  When
+    // R P < 2^32 for both layouts (narrow) every operand below is under 2^32,
+    // so 32-bit divisions suffice.
+    auto fdiv = [narrow](int64_t x, int64_t y) -> int64_t {
+        return narrow ? (int64_t)((uint32_t)x / (uint32_t)y) : x / y;
+    };
+    auto cdiv = [&](int64_t x, int64_t w) -> int64_t {
+        if (x < 0) return -fdiv(-x, w);
+        const int64_t q = fdiv(x, w);
+        return q + (q * w != x ? 1 : 0);
+    };
     // u in [a, b) whose B row lies in the range of process o
     auto keep_b = [&](int64_t o, int64_t a, int64_t b) -> int64_t {
         if (wbu == 0) return owner_of_row(rb0, d.P, d.Rb, narrow) == o ? b - a : 0;
-        const int64_t lo = (d.Rb * o) / d.P - rb0, hi = (d.Rb * (o + 1)) / d.P - rb0;
+        const int64_t lo = fdiv(d.Rb * o, d.P) - rb0, hi = fdiv(d.Rb * (o + 1), d.P) - rb0;
         const int64_t k0 = max<int64_t>(a, cdiv(lo, wbu)), k1 = min<int64_t>(b, cdiv(hi, wbu));
         return max<int64_t>(0, k1 - k0);
     };
@@ -120,7 +129,7 @@ __device__ __forceinline__ int64_t row_keep(const XposeDesc &d, const int *c, in
     for (int64_t u = u0, end = u0 + nu; u < end;) {
         const int64_t oa = owner_of_row(ra0 + u * wau, d.P, d.Ra, narrow);
         // first u past this piece: A row reaches the start of range oa + 1
-        const int64_t next = min<int64_t>(end, cdiv((d.Ra * (oa + 1)) / d.P - ra0, wau));
+        const int64_t next = min<int64_t>(end, cdiv(fdiv(d.Ra * (oa + 1), d.P) - ra0, wau));
         keep += keep_b(d.mu ? (int64_t)d.mu[oa] : oa, u, next);
         u = next;
     }
