@@ -727,8 +727,15 @@ StagedTileCfg make_tile(const fft_plan_impl *pl, int t, int seg_axis, bool pack)
         want(ra == 2 ? wa : ra, 4);
         want(2, 4);  // 16 slices: 128-byte runs, half the rank tasks of 32 (measured best)
     }
-    fill(1);
-    fill(0);
+    if (ra == 2 && !pack) {
+        // unpack tiles reading along the slices widen u before v: A's owner is
+        // computed per (slice, v), B's per (slice, u)
+        fill(0);
+        fill(1);
+    } else {
+        fill(1);
+        fill(0);
+    }
     fill(2);
     // a tile that is narrow along u pads every u-line: keep its LDS within 64 KB
     // by shrinking the largest axis that is not a lane axis (else the largest)
