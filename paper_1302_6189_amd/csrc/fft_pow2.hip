@@ -292,11 +292,20 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
         }
     }
     // (computed while the row loads are in flight) owner changes of this
-    // group's rows: thread r counts row v0 + r
+    // group's rows: thread r counts row v0 + r.  With rows < nv <= 64 wave 0
+    // holds every term and publishes the sum at once: work left for the end
+    // of the kernel delays the group's exit and costs more than it does here
     int moved = 0;
     if (d.count) {
         if (threadIdx.x == 0) moved_wg = 0;
         if (threadIdx.x < nv) moved = (int)(N - row_keep(d, bc, v0 + threadIdx.x, 0, N));
+        if constexpr (RW <= 64) {
+            if (threadIdx.x < 64) {
+                for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
+                if (threadIdx.x == 0 && moved)
+                    atomicAdd(d.counter + (blockIdx.x % kCountSlots) * kCountStride, (unsigned long long)moved);
+            }
+        }
     }
 
     run_passes<N, E, DIR, RL, 0>(v, lds + r * (N + N / 16), lane, tw);
@@ -338,15 +347,8 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
             st_nt(p, a0);
         }
     }
-    if (d.count) {
-        if constexpr (RW <= 64) {
-            // only rows < nv <= 64 counted: wave 0 holds every term
-            if (threadIdx.x < 64) {
-                for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
-                if (threadIdx.x == 0 && moved)
-                    atomicAdd(d.counter + (blockIdx.x % kCountSlots) * kCountStride, (unsigned long long)moved);
-            }
-        } else {
+    if constexpr (RW > 64) {
+        if (d.count) {
             for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
             if ((threadIdx.x & 63) == 0 && moved) atomicAdd(&moved_wg, moved);
             __syncthreads();
