@@ -56,7 +56,6 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
     const size_t rows_bytes = ((size_t)G * rw * S * sizeof(C) + 15) & ~(size_t)15;
     int64_t *abase = reinterpret_cast<int64_t *>(smem + rows_bytes);
     int64_t *bbase = abase + G;
-    int &moved_wg = *reinterpret_cast<int *>(bbase + G);
     const int64_t tiles_v = (d.Nv + rw - 1) / rw;
     const int64_t tv = unit % tiles_v;
     const int64_t g0 = (unit / tiles_v) * G;
@@ -67,7 +66,6 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
         int bc[3];
         slice_coords(d, g0 + gi, bc, &abase[gi], &bbase[gi]);
     }
-    if (d.count && threadIdx.x == 0) moved_wg = 0;
     __syncthreads();
 
     // rows (slice g0 + gi, v0 + r), rho = gi nv + r: N contiguous values each;
@@ -75,6 +73,9 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
     // kUnitItems loads are issued before any of them is stored to LDS, so a
     // thread keeps its whole share in flight (a unit holds at most 16 values
     // per thread).
+    // Every thread with rows to count (threadIdx.x < ng nv) has loads too.
+    int moved = 0;
+    bool counted = false;
     {
         const int drho = kThreads / N, dc = kThreads - drho * N;
         int rho = threadIdx.x / N, c = threadIdx.x - rho * N;
@@ -102,10 +103,21 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
                     }
                 }
             }
+            if (d.count && !counted) {  // owner changes, while the first loads are in flight
+                moved = tile_moved(d, g0, ng, 0, N, v0, nv);
+                counted = true;
+            }
 #pragma unroll
             for (int j = 0; j < kUnitItems; ++j)
                 if (at[j] >= 0) lds[at[j]] = val[j];
         }
+    }
+    if (d.count) {
+        // each wave publishes its sum at once: work left for the end of the
+        // unit would delay the group's next unit or its exit
+        for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
+        if ((threadIdx.x & 63) == 0 && moved)
+            atomicAdd(d.counter + (unit % kCountSlots) * kCountStride, (unsigned long long)moved);
     }
     __syncthreads();
     const int lanes = kThreads / (G * rw);
@@ -149,14 +161,6 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
                 ++gi;
             }
         }
-    }
-    if (d.count) {
-        int moved = tile_moved(d, g0, ng, 0, N, v0, nv);
-        for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
-        if ((threadIdx.x & 63) == 0 && moved) atomicAdd(&moved_wg, moved);
-        __syncthreads();
-        if (threadIdx.x == 0 && moved_wg)
-            atomicAdd(d.counter + (unit % kCountSlots) * kCountStride, (unsigned long long)moved_wg);
     }
     __syncthreads();  // the LDS block may be reused by the caller's next unit
 }

@@ -160,13 +160,12 @@ __host__ __device__ inline size_t xpose_tile_bytes(const XposeDesc &d, size_t es
 }
 
 // One tile of the transpose: tile index t (u fastest, then v, then slices);
-// smem holds the tile (plus owner vectors when counting) and one int.
+// smem holds the tile.
 template <typename C, int VU, int VV>
 __device__ __forceinline__ void xpose_tile(const C *__restrict__ in, C *__restrict__ out, const XposeDesc &d,
                                            uint32_t tile_index, unsigned char *smem)
 {
     C *tile = reinterpret_cast<C *>(smem);
-    int &moved_wg = *reinterpret_cast<int *>(smem + xpose_tile_bytes(d, sizeof(C)));
 
     const int TU = d.TU, TV = d.TV;
     const int ldt = TU + 1;
@@ -180,10 +179,13 @@ __device__ __forceinline__ void xpose_tile(const C *__restrict__ in, C *__restri
     const int nv = (int)min<int64_t>(TV, d.Nv - v0);
     const int ng = (int)min<int64_t>(d.G, d.nslices - g0);
 
-    int moved = 0;
     if (d.count) {
-        if (threadIdx.x == 0) moved_wg = 0;
-        moved = tile_moved(d, g0, ng, u0, nu, v0, nv);
+        // each wave publishes its sum at once: work left for the end of the
+        // tile would delay the group's exit
+        int moved = tile_moved(d, g0, ng, u0, nu, v0, nv);
+        for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
+        if ((threadIdx.x & 63) == 0 && moved)
+            atomicAdd(d.counter + (tile_index % kCountSlots) * kCountStride, (unsigned long long)moved);
     }
 
     // load: rows (g, v) of contiguous u-values
@@ -251,13 +253,6 @@ __device__ __forceinline__ void xpose_tile(const C *__restrict__ in, C *__restri
                 }
             }
         }
-    }
-    if (d.count) {
-        for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
-        if ((threadIdx.x & 63) == 0 && moved) atomicAdd(&moved_wg, moved);
-        __syncthreads();
-        if (threadIdx.x == 0 && moved_wg)
-            atomicAdd(d.counter + (tile_index % kCountSlots) * kCountStride, (unsigned long long)moved_wg);
     }
     __syncthreads();  // the LDS block may be reused by the caller's next unit
 }
