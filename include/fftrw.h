@@ -379,7 +379,9 @@ int fft_batch_destroy(fft_batch_t batch);
  * transposes of the given items on the current device and write the winners
  * to the JSON file cache_path: per row length, the radix order and rows per
  * work-group of the generic row kernel; per (u size, v size) transpose, the
- * tile shape.  The cache records the device architecture and library
+ * tile shape, and the radix order of the FFT step fused with it (the built-in
+ * order unless another is at least 3% faster); fused batch stages use the
+ * latter, separate stages the former.  The cache records the device architecture and library
  * version; fft_batch_plan ignores a cache whose tags do not match.  Uses
  * about 260 MB of device memory while it runs; synchronous.  flags: 0.
  */

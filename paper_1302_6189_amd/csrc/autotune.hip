@@ -5,7 +5,9 @@
 // most one pass more than the fewest, each in a few orders, together with the
 // 3s and 5s) and two choices of rows per work-group on the generic row kernel;
 // for every (u size, v size) pair of their transposes it times tile shapes
-// TU x TV (x G slices).  Timing uses HIP events on a private stream over a
+// TU x TV (x G slices), and the same radix orders in the FFT step fused with
+// that transpose (the unit the batched form runs by default: its best radix
+// order differs from the separate row kernel's).  Timing uses HIP events on a private stream over a
 // synthetic array of about 16 M complex values.  The winners are written to a
 // small JSON cache tagged with the device architecture and library version;
 // plans built with that cache (fft_batch_plan's tune_cache) use them.
@@ -32,6 +34,9 @@ hipError_t launch_twiddles(void *out, int64_t n, bool fp64, hipStream_t s);
 hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in, void *out, double scale,
                            hipStream_t s);
 hipError_t launch_xpose(const XposeDesc &d, size_t esz, const void *in, void *out, hipStream_t s);
+hipError_t launch_fft_xpose_generic(const FftDesc &f, const XposeDesc &d, bool fp64, int dir, const void *in,
+                                    void *out, double scale, hipStream_t s);
+int factor_radices(int64_t n, int *rad);
 
 std::string tune_device_name()
 {
@@ -209,6 +214,13 @@ bool tune_load(const std::string &path, const std::string &device, const std::st
         if (nu.size() != 1 || nv.size() != 1 || tu.size() != 1 || tv.size() != 1 || g.size() != 1) continue;
         t.tiles[{(int)nu[0], (int)nv[0]}] = TileTune{(int)tu[0], (int)tv[0], (int)g[0]};
     }
+    for (const std::string &o : json_objects(txt, "fused")) {
+        auto n = json_ints(o, "n"), nv = json_ints(o, "nv"), rad = json_ints(o, "radix");
+        if (n.size() != 1 || nv.size() != 1 || rad.empty()) continue;
+        std::vector<int> r;
+        for (long long x : rad) r.push_back((int)x);
+        t.fused[{(int)n[0], (int)nv[0]}] = r;
+    }
     *out = t;
     return true;
 }
@@ -231,6 +243,15 @@ bool tune_save(const std::string &path, const TuneTable &t)
     for (const auto &kv : t.tiles) {
         f << (first ? "\n" : ",\n") << "    {\"nu\": " << kv.first.first << ", \"nv\": " << kv.first.second
           << ", \"tu\": " << kv.second.TU << ", \"tv\": " << kv.second.TV << ", \"g\": " << kv.second.G << "}";
+        first = false;
+    }
+    f << "\n  ],\n  \"fused\": [";
+    first = true;
+    for (const auto &kv : t.fused) {
+        f << (first ? "\n" : ",\n") << "    {\"n\": " << kv.first.first << ", \"nv\": " << kv.first.second
+          << ", \"radix\": [";
+        for (size_t i = 0; i < kv.second.size(); ++i) f << (i ? ", " : "") << kv.second[i];
+        f << "]}";
         first = false;
     }
     f << "\n  ]\n}\n";
@@ -351,6 +372,50 @@ extern "C" int fft_autotune(int n, const fft_item_desc *items, const char *cache
             }
         }
         if (best > 0.f) table.tiles[pr] = win;
+        // the FFT step along u fused with this transpose, per radix order
+        if (Nu + 1 > 4096) continue;
+        if (launch_twiddles(tw, Nu, false, tm.s) != hipSuccess) {
+            rc = fail(FFTRW_E_DEVICE, "autotuner twiddles");
+            break;
+        }
+        XposeDesc x;
+        std::memset(&x, 0, sizeof(x));
+        x.Nu = Nu;
+        x.Nv = Nv;
+        x.a_sv = Nu;
+        x.b_su = Nv;
+        x.nbat = 1;
+        x.bsize[0] = S;
+        x.ba[0] = x.bb[0] = (int64_t)Nu * Nv;
+        x.nslices = S;
+        // the built-in order first; another wins only by a clear margin (3%),
+        // since the times of near-equal orders differ by noise on this array
+        int def[kMaxPasses];
+        const int ndef = factor_radices(Nu, def);
+        std::vector<std::vector<int>> cands{std::vector<int>(def, def + ndef)};
+        for (const std::vector<int> &rad : row_candidates(Nu))
+            if (rad != cands[0]) cands.push_back(rad);
+        float fdef = -1.f, fbest = -1.f;
+        std::vector<int> fwin;
+        for (const std::vector<int> &rad : cands) {
+            FftDesc f;
+            std::memset(&f, 0, sizeof(f));
+            f.N = Nu;
+            f.npass = (int)rad.size();
+            for (size_t q = 0; q < rad.size(); ++q) f.radix[q] = rad[q];
+            f.nrows = S * Nv;
+            f.tw = tw;
+            const float ms = tm.time([&] { return launch_fft_xpose_generic(f, x, false, -1, a, b, 1.0, tm.s); }, 10);
+            if (ms <= 0.f) continue;
+            if (fdef < 0.f) {
+                fdef = fbest = ms;
+                fwin = rad;
+            } else if (ms < fbest && ms < 0.97f * fdef) {
+                fbest = ms;
+                fwin = rad;
+            }
+        }
+        if (fbest > 0.f) table.fused[pr] = fwin;
     }
     (void)hipFree(a);
     (void)hipFree(b);

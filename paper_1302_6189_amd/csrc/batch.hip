@@ -319,6 +319,25 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
                 if (t < nx) {
                     d.xp[t] = p->xp[t];
                     const int N = d.fft[t].N;
+                    if (tuned) {
+                        // the radix order the autotuner timed in the fused unit
+                        // (it differs from the separate row kernel's), checked
+                        // as the plan checks the row kernel's
+                        auto ft = tune.fused.find({N, (int)d.xp[t].Nv});
+                        if (ft != tune.fused.end()) {
+                            const std::vector<int> &rad = ft->second;
+                            int64_t prod = 1;
+                            bool ok = !rad.empty() && (int)rad.size() <= kMaxPasses;
+                            for (int r : rad) {
+                                ok = ok && (r == 2 || r == 3 || r == 4 || r == 5 || r == 8 || r == 16);
+                                prod *= r;
+                            }
+                            if (ok && prod == N) {
+                                d.fft[t].npass = (int)rad.size();
+                                for (int q = 0; q < d.fft[t].npass; ++q) d.fft[t].radix[q] = rad[q];
+                            }
+                        }
+                    }
                     int rw = 1, G = 1;
                     fused_unit_shape(N, d.xp[t].Nv, d.xp[t].nslices, 4096, &rw, &G);
                     d.frw[t] = rw;

@@ -249,7 +249,7 @@ extern "C" {
 
 const char *fft_last_error(void) { return g_last_error.c_str(); }
 
-const char *fft_version(void) { return "fftrw 0.1.0 (gfx950)"; }
+const char *fft_version(void) { return "fftrw 0.2.0 (gfx950)"; }
 
 int fft_decomp(int M, const int64_t *dims, int64_t P, const int8_t *perm, int64_t myid, int *level,
                int64_t *xs, int64_t *xe, int64_t *start, int64_t *end)

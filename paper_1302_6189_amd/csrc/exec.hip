@@ -48,30 +48,9 @@ int staged_run(fft_plan_impl *pl, int t, const void *in, void *out, hipStream_t 
 int staged_part(fft_plan_impl *pl, int t, int part, const void *in, void *out, hipStream_t s);
 void staged_free(fft_plan_impl *pl);
 
-namespace {
-
-int hip_fail(hipError_t e, const char *what)
-{
-    std::string m = std::string(what) + ": " + hipGetErrorString(e);
-    return fail(FFTRW_E_DEVICE, m);
-}
-
-#define HIP_TRY(expr, what)                     \
-    do {                                        \
-        hipError_t _e = (expr);                 \
-        if (_e != hipSuccess) return hip_fail(_e, what); \
-    } while (0)
-
-bool smooth235(i64 n)
-{
-    if (n < 1) return false;
-    for (int p : {2, 3, 5})
-        while (n % p == 0) n /= p;
-    return n == 1;
-}
-
 // Radix factorisation of a row length: powers of two as 8s with a 16, 4 or 2
-// to finish, then 3s and 5s.  Returns the number of passes.
+// to finish, then 3s and 5s.  Returns the number of passes.  The autotuner
+// times this built-in order too.
 int factor_radices(i64 n, int *rad)
 {
     int np = 0;
@@ -103,6 +82,29 @@ int factor_radices(i64 n, int *rad)
     for (int i = 0; i < e5; ++i) rad[np++] = 5;
     return np;
 }
+
+namespace {
+
+int hip_fail(hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(FFTRW_E_DEVICE, m);
+}
+
+#define HIP_TRY(expr, what)                     \
+    do {                                        \
+        hipError_t _e = (expr);                 \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+bool smooth235(i64 n)
+{
+    if (n < 1) return false;
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
 
 i64 pow2ceil(i64 x)
 {

@@ -22,6 +22,7 @@ struct TuneTable {
     std::string device, version;
     std::map<int, RowTune> rows;                       // by row length
     std::map<std::pair<int, int>, TileTune> tiles;     // by (Nu, Nv)
+    std::map<std::pair<int, int>, std::vector<int>> fused;  // radix order of a fused step, by (N, Nv)
 };
 
 // Load a cache written by fft_autotune; false if missing, unreadable, or

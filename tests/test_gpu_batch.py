@@ -108,6 +108,11 @@ def test_autotuned_batch(gpu_lib, tmp_path):
     assert {r["n"] for r in rec["rows"]} == lengths
     for r in rec["rows"]:
         assert np.prod(r["radix"]) == r["n"]
+    # radix orders timed in the fused FFT step + transpose, per (N, N_v) pair
+    assert rec["fused"]
+    assert {r["n"] for r in rec["fused"]} == lengths
+    for r in rec["fused"]:
+        assert np.prod(r["radix"]) == r["n"]
     xs = [inputs.uniform(d, 300 + i, np.complex64) for i, (d, _) in enumerate(items)]
     b = fftrw.Batch(items, flags=fftrw.FLAG_COUNT_MOVED, tune_cache=cache)
     ins, outs = _run(b, xs)
