@@ -135,6 +135,46 @@ def test_autotuned_batch(gpu_lib, tmp_path):
         assert np.array_equal(to_host(outs2[i]), to_host(outs3[i]))
 
 
+def test_fused_radix_cache_entries(gpu_lib, tmp_path):
+    # the fused stages take the cache's per-(N, N_v) radix orders only when
+    # they are valid (radices of the kernel, product N); otherwise the batch
+    # keeps its built-in orders and computes bit for bit what an untuned
+    # batch does
+    import json
+    items = inputs.batch_items(12, seed=9)
+    xs = [inputs.uniform(d, 500 + i, np.complex64) for i, (d, _) in enumerate(items)]
+    cache = str(tmp_path / "tune.json")
+    fftrw.fft_autotune(items, cache)
+    with open(cache) as f:
+        rec = json.load(f)
+    rec["rows"], rec["tiles"] = [], []
+    plain = fftrw.Batch(items)
+    _, ref_outs = _run(plain, xs)
+    bad = dict(rec, fused=[dict(r, radix=[7] if i % 2 else r["radix"] + [2]) for i, r in enumerate(rec["fused"])])
+    with open(cache, "w") as f:
+        json.dump(bad, f)
+    b = fftrw.Batch(items, tune_cache=cache)
+    _, outs = _run(b, xs)
+    for i in range(len(items)):
+        assert np.array_equal(to_host(outs[i]), to_host(ref_outs[i])), i
+    # valid orders (every order reversed: still the product N) are applied
+    good = dict(rec, fused=[dict(r, radix=r["radix"][::-1]) for r in rec["fused"]])
+    with open(cache, "w") as f:
+        json.dump(good, f)
+    b2 = fftrw.Batch(items, flags=fftrw.FLAG_COUNT_MOVED, tune_cache=cache)
+    _, outs2 = _run(b2, xs)
+    st = b2.stats()
+    assert st["error"] == 0 and st["moved"] == st["analytic"]
+    differs = False
+    for i, (dims, P) in enumerate(items):
+        order = fftrw.fft_order_search(dims, P)["best_order"]
+        ref = dft.fftn_direct(xs[i], orders.fft_axis_sequence(order))
+        y = to_host(outs2[i])
+        assert dft.rel_l2(y, ref) < 1e-5, i
+        differs = differs or not np.array_equal(y, to_host(ref_outs[i]))
+    assert differs  # some reversed order changed the arithmetic
+
+
 @pytest.mark.parametrize("leave", [False, True])
 def test_fused_schedule_matches_separate_stages(gpu_lib, leave):
     # FFT steps fused with their transposes run the same passes on the same data
