@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(kThreads)
                 const bool last = st == it.M - 1;
                 const float sc = DIR > 0 && last ? it.inv_scale : 1.f;
                 if (st < it.nx)
-                    fft_xpose_unit<float2, DIR>(src, dst, it.fft[st], it.xp[st], it.frw[st], it.fg[st], local,
+                    fft_xpose_unit<float2, DIR, true>(src, dst, it.fft[st], it.xp[st], it.frw[st], it.fg[st], local,
                                                 sc, DIR > 0 && last, smem);
                 else
                     fft_rows_block<float2, DIR>(src, dst, it.fft[st], local, sc, DIR > 0 && last,

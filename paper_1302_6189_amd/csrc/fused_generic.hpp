@@ -44,8 +44,117 @@ __host__ __device__ inline size_t fused_unit_bytes(int N, int rw, int G, size_t 
     return (((size_t)G * rw * (N + 1) * esz + 15) & ~(size_t)15) + (size_t)G * 16 + 16;
 }
 
+// Rows (slice g0 + gi, v0 + r) of a unit into LDS (row rho = gi rw + r at
+// rho S), W consecutive values per access (W = 2: 16-byte loads of complex64,
+// N even, so every row starts on an even element).  Group e = rho N / W + c
+// is stepped by kThreads without divisions; up to kUnitItems values are in
+// flight per thread before any is stored to LDS (a unit holds at most 16
+// values per thread).  The owner changes of the unit's rows are counted
+// while the first loads are in flight: every thread with rows to count
+// (threadIdx.x < ng nv) has loads too.
+template <int W, typename C>
+__device__ __forceinline__ void load_unit_rows(const C *__restrict__ in, C *lds, const FftDesc &f,
+                                               const XposeDesc &d, const int64_t *abase, int S, int rw, int nv,
+                                               int ng, int64_t g0, int64_t v0, int &moved)
+{
+    constexpr int ITEMS = kUnitItems / W;
+    const int N = f.N;
+    const int NW = N / W;
+    const int drho = kThreads / NW, dc = kThreads - drho * NW;
+    int rho = threadIdx.x / NW, c = threadIdx.x - rho * NW;
+    int gi = rho / nv, r = rho - gi * nv;
+    const int drg = drho / nv, drr = drho - drg * nv;
+    bool counted = false;
+    while (gi < ng) {
+        C val[ITEMS][W];
+        int at[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            at[j] = -1;
+            if (gi < ng) {
+                at[j] = (gi * rw + r) * S + c * W;
+                const C *p = in + abase[gi] + (v0 + r) * d.a_sv + c * W;
+                if constexpr (W == 2) {
+                    const xf4 w = __builtin_nontemporal_load(reinterpret_cast<const xf4 *>(p));
+                    val[j][0] = mk<C>(w.x, w.y);
+                    val[j][1] = mk<C>(w.z, w.w);
+                } else {
+                    val[j][0] = xld(p);
+                }
+                c += dc;
+                gi += drg;
+                r += drr;
+                if (c >= NW) {
+                    c -= NW;
+                    ++r;
+                }
+                while (r >= nv) {
+                    r -= nv;
+                    ++gi;
+                }
+            }
+        }
+        if (d.count && !counted) {
+            moved = tile_moved(d, g0, ng, 0, N, v0, nv);
+            counted = true;
+        }
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            if (at[j] >= 0) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) lds[at[j] + w] = val[j][w];
+            }
+    }
+}
+
+// The transformed rows to B: frequency k of row (gi, r) at (slice g0 + gi,
+// u = k, v = v0 + r).  Group e = (gi N + k) nv / W + r / W, W consecutive v
+// per access (W = 2: 16-byte stores of complex64, nv and every run start
+// even).
+template <int W, typename C>
+__device__ __forceinline__ void store_unit_runs(C *__restrict__ out, const C *lds, const XposeDesc &d,
+                                                const int64_t *bbase, int N, int S, int rw, int nv, int ng,
+                                                int64_t v0, typename RealOf<C>::type scale, bool do_scale)
+{
+    const int nvw = nv / W;
+    const int dkk = kThreads / nvw, dr = kThreads - dkk * nvw;
+    int kk = threadIdx.x / nvw, r = threadIdx.x - kk * nvw;
+    int gi = kk / N, k = kk - gi * N;
+    const int dg = dkk / N, dk = dkk - dg * N;
+    while (gi < ng) {
+        C q[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            q[w] = lds[(gi * rw + r * W + w) * S + k];
+            if (do_scale) q[w] = cscale(q[w], scale);
+        }
+        C *p = out + bbase[gi] + (int64_t)k * d.b_su + v0 + r * W;
+        if constexpr (W == 2) {
+            const xf4 w = {q[0].x, q[0].y, q[1].x, q[1].y};
+            __builtin_nontemporal_store(w, reinterpret_cast<xf4 *>(p));
+        } else {
+            xst(p, q[0]);
+        }
+        r += dr;
+        gi += dg;
+        k += dk;
+        if (r >= nvw) {
+            r -= nvw;
+            ++k;
+        }
+        if (k >= N) {
+            k -= N;
+            ++gi;
+        }
+    }
+}
+
 // Unit `unit` of a fused step: v-block unit % tiles_v of G consecutive slices.
-template <typename C, int DIR>
+// PAIR_LOADS reads even rows of complex64 with 16-byte loads.  Measured on
+// MI355X, that makes the batched form's persistent kernel (rows of 12..192)
+// 10% faster but single plans (rows of 300..480, 8-16 rows per unit) 16%
+// slower, so each caller picks; 16-byte stores help both.
+template <typename C, int DIR, bool PAIR_LOADS = false>
 __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__restrict__ out, const FftDesc &f,
                                                const XposeDesc &d, int rw, int G, int64_t unit,
                                                typename RealOf<C>::type scale, bool do_scale, unsigned char *smem)
@@ -68,49 +177,17 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
     }
     __syncthreads();
 
-    // rows (slice g0 + gi, v0 + r), rho = gi nv + r: N contiguous values each;
-    // element e = rho N + c, stepped by kThreads without divisions.  Up to
-    // kUnitItems loads are issued before any of them is stored to LDS, so a
-    // thread keeps its whole share in flight (a unit holds at most 16 values
-    // per thread).
-    // Every thread with rows to count (threadIdx.x < ng nv) has loads too.
+    // rows (slice g0 + gi, v0 + r), rho = gi nv + r: N contiguous values each,
+    // read in 16-byte pairs when asked for and N is even (complex64)
     int moved = 0;
-    bool counted = false;
-    {
-        const int drho = kThreads / N, dc = kThreads - drho * N;
-        int rho = threadIdx.x / N, c = threadIdx.x - rho * N;
-        int gi = rho / nv, r = rho - gi * nv;
-        const int drg = drho / nv, drr = drho - drg * nv;
-        while (gi < ng) {
-            C val[kUnitItems];
-            int at[kUnitItems];
-#pragma unroll
-            for (int j = 0; j < kUnitItems; ++j) {
-                at[j] = -1;
-                if (gi < ng) {
-                    at[j] = (gi * rw + r) * S + c;
-                    val[j] = xld(in + abase[gi] + (v0 + r) * d.a_sv + c);
-                    c += dc;
-                    gi += drg;
-                    r += drr;
-                    if (c >= N) {
-                        c -= N;
-                        ++r;
-                    }
-                    while (r >= nv) {
-                        r -= nv;
-                        ++gi;
-                    }
-                }
-            }
-            if (d.count && !counted) {  // owner changes, while the first loads are in flight
-                moved = tile_moved(d, g0, ng, 0, N, v0, nv);
-                counted = true;
-            }
-#pragma unroll
-            for (int j = 0; j < kUnitItems; ++j)
-                if (at[j] >= 0) lds[at[j]] = val[j];
+    if constexpr (sizeof(C) == 8 && PAIR_LOADS) {
+        if (N % 2 == 0) {
+            load_unit_rows<2>(in, lds, f, d, abase, S, rw, nv, ng, g0, v0, moved);
+        } else {
+            load_unit_rows<1>(in, lds, f, d, abase, S, rw, nv, ng, g0, v0, moved);
         }
+    } else {
+        load_unit_rows<1>(in, lds, f, d, abase, S, rw, nv, ng, g0, v0, moved);
     }
     if (d.count) {
         // each wave publishes its sum at once: work left for the end of the
@@ -138,29 +215,17 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
         }
         Ns *= f.radix[p];
     }
-    // frequency k of row (gi, r) goes to B at (slice g0 + gi, u = k, v = v0 + r):
-    // element e = (gi N + k) nv + r, runs of nv consecutive v
-    {
-        const int dkk = kThreads / nv, dr = kThreads - dkk * nv;
-        int kk = threadIdx.x / nv, r = threadIdx.x - kk * nv;
-        int gi = kk / N, k = kk - gi * N;
-        const int dg = dkk / N, dk = dkk - dg * N;
-        while (gi < ng) {
-            C q = lds[(gi * rw + r) * S + k];
-            if (do_scale) q = cscale(q, scale);
-            xst(out + bbase[gi] + (int64_t)k * d.b_su + v0 + r, q);
-            r += dr;
-            gi += dg;
-            k += dk;
-            if (r >= nv) {
-                r -= nv;
-                ++k;
-            }
-            if (k >= N) {
-                k -= N;
-                ++gi;
-            }
+    // frequency k of row (gi, r) goes to B at (slice g0 + gi, u = k, v = v0 + r),
+    // runs of nv consecutive v; 16-byte pairs of v when N_v and rw are even
+    // (complex64: every run then starts on an even element)
+    if constexpr (sizeof(C) == 8) {
+        if (d.Nv % 2 == 0 && rw % 2 == 0) {
+            store_unit_runs<2>(out, lds, d, bbase, N, S, rw, nv, ng, v0, scale, do_scale);
+        } else {
+            store_unit_runs<1>(out, lds, d, bbase, N, S, rw, nv, ng, v0, scale, do_scale);
         }
+    } else {
+        store_unit_runs<1>(out, lds, d, bbase, N, S, rw, nv, ng, v0, scale, do_scale);
     }
     __syncthreads();  // the LDS block may be reused by the caller's next unit
 }
