@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(kThreads)
                 const bool last = st == it.M - 1;
                 const float sc = DIR > 0 && last ? it.inv_scale : 1.f;
                 if (st < it.nx)
-                    fft_xpose_unit<float2, DIR, true>(src, dst, it.fft[st], it.xp[st], it.frw[st], it.fg[st], local,
+                    fft_xpose_unit<float2, DIR>(src, dst, it.fft[st], it.xp[st], it.frw[st], it.fg[st], local,
                                                 sc, DIR > 0 && last, smem);
                 else
                     fft_rows_block<float2, DIR>(src, dst, it.fft[st], local, sc, DIR > 0 && last,
@@ -308,7 +308,7 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
         d.inv_scale = (float)(1.0 / (double)p->T);
         int64_t units = 0;
         // fused schedule: one unit = RW rows consecutive in v of one slice, the
-        // largest power of two with RW (N + 1) <= 4096 that the v axis can fill
+        // largest power of two with RW (N + padding) <= 4096 that the v axis can fill
         d.fused = !(flags & FFTRW_FLAG_BATCH_NO_FUSE);
         if (d.fused) {
             d.nstage = it.M;
@@ -339,7 +339,7 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
                         }
                     }
                     int rw = 1, G = 1;
-                    fused_unit_shape(N, d.xp[t].Nv, d.xp[t].nslices, 4096, &rw, &G);
+                    fused_unit_shape(N, 8, d.xp[t].Nv, d.xp[t].nslices, 4096, &rw, &G);
                     d.frw[t] = rw;
                     d.fg[t] = G;
                     d.src[t] = t == 0 ? 0 : cur;

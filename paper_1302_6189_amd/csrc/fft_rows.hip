@@ -78,7 +78,7 @@ hipError_t launch_fft_xpose_generic(const FftDesc &f, const XposeDesc &d, bool f
                                     void *out, double scale, hipStream_t s)
 {
     int rw = 1, G = 1;
-    fused_unit_shape(f.N, d.Nv, d.nslices, fp64 ? 2048 : 4096, &rw, &G);
+    fused_unit_shape(f.N, fp64 ? 16 : 8, d.Nv, d.nslices, fp64 ? 2048 : 4096, &rw, &G);
     const int64_t nblk = ((d.Nv + rw - 1) / rw) * ((d.nslices + G - 1) / G);
     if (nblk <= 0) return hipSuccess;
     if (nblk >= (int64_t)0x7fffffff) return hipErrorInvalidValue;

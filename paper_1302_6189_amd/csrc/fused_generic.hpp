@@ -24,16 +24,23 @@ namespace fftrw {
 
 constexpr int kUnitItems = 16;  // loads in flight per thread while a unit is staged
 
+// LDS pitch of a unit's rows: one value of padding, two for even complex64
+// rows so that every row starts 16 bytes aligned and a 16-byte pair of
+// values goes to LDS in one store (two 8-byte stores of the pairs conflict
+// on the LDS banks)
+__host__ __device__ inline int unit_pitch(int N, size_t esz) { return esz == 8 && N % 2 == 0 ? N + 2 : N + 1; }
+
 // Shape of a fused unit for rows of length N: RW rows per slice (a power of
 // two covering the v extent when it can) and G slices, so that a unit holds at
-// most `budget` values (4096 complex64, 2048 complex128) and every row keeps at
-// least one lane of the 256-thread group.
-inline void fused_unit_shape(int N, int64_t Nv, int64_t nslices, int budget, int *rw, int *G)
+// most `budget` values with their padding (4096 complex64, 2048 complex128)
+// and every row keeps at least one lane of the 256-thread group.
+inline void fused_unit_shape(int N, size_t esz, int64_t Nv, int64_t nslices, int budget, int *rw, int *G)
 {
+    const int P = unit_pitch(N, esz);
     int r = 1;
-    while (r * 2 <= 256 && (int64_t)r * 2 * (N + 1) <= budget && r * 2 <= 2 * Nv - 1) r *= 2;
+    while (r * 2 <= 256 && (int64_t)r * 2 * P <= budget && r * 2 <= 2 * Nv - 1) r *= 2;
     int g = 1;
-    while (g * 2 * r <= 256 && (int64_t)g * 2 * r * (N + 1) <= budget && g * 2 <= 2 * nslices - 1) g *= 2;
+    while (g * 2 * r <= 256 && (int64_t)g * 2 * r * P <= budget && g * 2 <= 2 * nslices - 1) g *= 2;
     *rw = r;
     *G = g;
 }
@@ -41,12 +48,13 @@ inline void fused_unit_shape(int N, int64_t Nv, int64_t nslices, int budget, int
 // LDS bytes of a fused unit: G * RW padded rows, the slices' bases, one int
 __host__ __device__ inline size_t fused_unit_bytes(int N, int rw, int G, size_t esz)
 {
-    return (((size_t)G * rw * (N + 1) * esz + 15) & ~(size_t)15) + (size_t)G * 16 + 16;
+    return (((size_t)G * rw * unit_pitch(N, esz) * esz + 15) & ~(size_t)15) + (size_t)G * 16 + 16;
 }
 
 // Rows (slice g0 + gi, v0 + r) of a unit into LDS (row rho = gi rw + r at
-// rho S), W consecutive values per access (W = 2: 16-byte loads of complex64,
-// N even, so every row starts on an even element).  Group e = rho N / W + c
+// rho S), W consecutive values per access (W = 2: 16-byte loads and LDS
+// stores of complex64, N and S even, so every row starts on an even element
+// in HBM and 16 bytes aligned in LDS).  Group e = rho N / W + c
 // is stepped by kThreads without divisions; up to kUnitItems values are in
 // flight per thread before any is stored to LDS (a unit holds at most 16
 // values per thread).  The owner changes of the unit's rows are counted
@@ -101,8 +109,12 @@ __device__ __forceinline__ void load_unit_rows(const C *__restrict__ in, C *lds,
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j)
             if (at[j] >= 0) {
-#pragma unroll
-                for (int w = 0; w < W; ++w) lds[at[j] + w] = val[j][w];
+                if constexpr (W == 2) {
+                    const xf4 w4 = {val[j][0].x, val[j][0].y, val[j][1].x, val[j][1].y};
+                    *reinterpret_cast<xf4 *>(lds + at[j]) = w4;
+                } else {
+                    lds[at[j]] = val[j][0];
+                }
             }
     }
 }
@@ -150,17 +162,13 @@ __device__ __forceinline__ void store_unit_runs(C *__restrict__ out, const C *ld
 }
 
 // Unit `unit` of a fused step: v-block unit % tiles_v of G consecutive slices.
-// PAIR_LOADS reads even rows of complex64 with 16-byte loads.  Measured on
-// MI355X, that makes the batched form's persistent kernel (rows of 12..192)
-// 10% faster but single plans (rows of 300..480, 8-16 rows per unit) 16%
-// slower, so each caller picks; 16-byte stores help both.
-template <typename C, int DIR, bool PAIR_LOADS = false>
+template <typename C, int DIR>
 __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__restrict__ out, const FftDesc &f,
                                                const XposeDesc &d, int rw, int G, int64_t unit,
                                                typename RealOf<C>::type scale, bool do_scale, unsigned char *smem)
 {
     const int N = f.N;
-    const int S = N + 1;
+    const int S = unit_pitch(N, sizeof(C));
     C *lds = reinterpret_cast<C *>(smem);
     const size_t rows_bytes = ((size_t)G * rw * S * sizeof(C) + 15) & ~(size_t)15;
     int64_t *abase = reinterpret_cast<int64_t *>(smem + rows_bytes);
@@ -178,9 +186,9 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
     __syncthreads();
 
     // rows (slice g0 + gi, v0 + r), rho = gi nv + r: N contiguous values each,
-    // read in 16-byte pairs when asked for and N is even (complex64)
+    // read in 16-byte pairs when N is even (complex64)
     int moved = 0;
-    if constexpr (sizeof(C) == 8 && PAIR_LOADS) {
+    if constexpr (sizeof(C) == 8) {
         if (N % 2 == 0) {
             load_unit_rows<2>(in, lds, f, d, abase, S, rw, nv, ng, g0, v0, moved);
         } else {
