@@ -254,6 +254,8 @@ def batched_form(reps):
            "device_counts_match_analytic": counts_ok,
            "persistent_graph": {"ms": round(ms_batch, 4), "GFLOPs": round(flops / (ms_batch * 1e-3) / 1e9, 1),
                                 "algorithmic_GBs": round(alg_bytes / (ms_batch * 1e-3) / 1e9, 1),
+                                # fused stages: one read and one write of every point per step
+                                "fused_hbm_GBs": round(alg_bytes / 2 / (ms_batch * 1e-3) / 1e9, 1),
                                 "autotuned": True, "autotune_s": round(tune_s, 2),
                                 "ms_without_autotune": round(ms_untuned, 4)},
            "per_item_loop": {"ms": round(ms_loop, 4), "GFLOPs": round(flops / (ms_loop * 1e-3) / 1e9, 1),
