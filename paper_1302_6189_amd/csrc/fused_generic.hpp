@@ -1,12 +1,12 @@
 // fused_generic.hpp -- one FFT step fused with the transpose that follows it,
-// for rows of any 2,3,5-smooth length (device code of the persistent batched
-// kernel).
+// for rows of any 2,3,5-smooth length (device code shared by single plans and
+// the persistent batched kernel).
 //
 // A unit takes RW rows of layout A that are consecutive in v (the last axis of
 // the next layout B) in each of G consecutive batch slices (G > 1 when the
 // rows are short): each row is contiguous along u
-// (the FFT axis), rows sit a_sv apart.  The rows are staged in LDS (row stride
-// N + 1, so reading a column touches distinct banks), transformed by the same
+// (the FFT axis), rows sit a_sv apart.  The rows are staged in LDS (row pitch
+// N + 1, or N + 2 for even complex64 rows, see unit_pitch), transformed by the same
 // Stockham passes as fft_rows_block, and written in layout B: for every
 // frequency k the RW results form one run of consecutive v.  One HBM round trip
 // replaces two (the FFT step's and the transpose's).  Owner changes are counted
