@@ -75,7 +75,7 @@ __device__ __forceinline__ float2 *batch_buf(const BatchItemDev &it, int kind)
     return kind == 0 ? const_cast<float2 *>(it.in) : (kind == 1 ? it.out : it.work);
 }
 
-template <int DIR>
+template <int DIR, bool TW_LDS>
 __global__ void __launch_bounds__(kThreads)
     batch_kernel(const BatchItemDev *__restrict__ items, const BatchTask *__restrict__ tasks,
                  const int *__restrict__ level_task0, const int64_t *__restrict__ level_units, int nlevels,
@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(kThreads)
                 const bool last = st == it.M - 1;
                 const float sc = DIR > 0 && last ? it.inv_scale : 1.f;
                 if (st < it.nx)
-                    fft_xpose_unit<float2, DIR>(src, dst, it.fft[st], it.xp[st], it.frw[st], it.fg[st], local,
+                    fft_xpose_unit<float2, DIR, TW_LDS>(src, dst, it.fft[st], it.xp[st], it.frw[st], it.fg[st], local,
                                                 sc, DIR > 0 && last, smem);
                 else
                     fft_rows_block<float2, DIR>(src, dst, it.fft[st], local, sc, DIR > 0 && last,
@@ -212,6 +212,7 @@ struct fft_batch_impl {
     bool pointers_set = false;
     bool tuned = false;  // a matching autotuner cache was applied
     bool any_fused = false;
+    bool tw_lds = false;  // fused units stage their twiddle tables in LDS
 };
 
 namespace {
@@ -245,12 +246,15 @@ int batch_enqueue(fft_batch_impl *b, int dir, hipStream_t s)
     if (e != hipSuccess) return batch_fail_hip(e, "batch reset launch");
     BatchCounters *ctr = reinterpret_cast<BatchCounters *>(b->d_ctr);
     const int nl = (int)b->level_units.size();
-    if (dir < 0)
-        hipLaunchKernelGGL(batch_kernel<-1>, dim3(b->grid), dim3(kThreads), b->lds, s, b->d_items, b->d_tasks,
-                           b->d_level_task0, b->d_level_units, nl, ctr);
-    else
-        hipLaunchKernelGGL(batch_kernel<1>, dim3(b->grid), dim3(kThreads), b->lds, s, b->d_items, b->d_tasks,
-                           b->d_level_task0, b->d_level_units, nl, ctr);
+#define FFTRW_LAUNCH(D, T)                                                                                   \
+    hipLaunchKernelGGL((batch_kernel<D, T>), dim3(b->grid), dim3(kThreads), b->lds, s, b->d_items, b->d_tasks, \
+                       b->d_level_task0, b->d_level_units, nl, ctr)
+    if (dir < 0) {
+        if (b->tw_lds) FFTRW_LAUNCH(-1, true); else FFTRW_LAUNCH(-1, false);
+    } else {
+        if (b->tw_lds) FFTRW_LAUNCH(1, true); else FFTRW_LAUNCH(1, false);
+    }
+#undef FFTRW_LAUNCH
     e = hipGetLastError();
     if (e != hipSuccess) return batch_fail_hip(e, "batch kernel launch");
     return FFTRW_OK;
@@ -286,7 +290,8 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
     const unsigned pflags = flags & (FFTRW_FLAG_COUNT_MOVED | FFTRW_FLAG_LEAVE_PERMUTED);
     const bool leave = (flags & FFTRW_FLAG_LEAVE_PERMUTED) != 0;
     b->h_items.resize(n);
-    size_t lds = 16;
+    size_t lds = 16, lds_tw = 16;  // LDS per group without and with staged twiddles
+    bool tw_fits = true;          // every fused step's table fits (unit_tw_fits)
     int max_stage = 0;
     for (int i = 0; i < n; ++i) {
         const fft_item_desc &it = items[i];
@@ -346,7 +351,9 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
                     d.dst[t] = ((nx - 1 - t) % 2 == 0) ? 1 : 2;
                     cur = d.dst[t];
                     units += ((d.xp[t].Nv + rw - 1) / rw) * ((d.xp[t].nslices + G - 1) / G);
-                    lds = std::max(lds, fused_unit_bytes(N, rw, G, 8));
+                    lds = std::max(lds, fused_unit_bytes(N, rw, G, 8, false));
+                    lds_tw = std::max(lds_tw, fused_unit_bytes(N, rw, G, 8, true));
+                    tw_fits = tw_fits && unit_tw_fits(N, 8);
                 } else {
                     // LEAVE_PERMUTED: the last FFT step runs in place on the output
                     d.src[t] = 1;
@@ -403,7 +410,10 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
         b->total += lvl;
     }
     b->level_task0.push_back((int)b->h_tasks.size());
-    b->lds = (lds + 15) & ~(size_t)15;
+    // twiddles in LDS when every fused step's table fits; the groups of the
+    // separate stages need no more LDS either way
+    b->tw_lds = b->any_fused && tw_fits;
+    b->lds = (std::max(lds, b->tw_lds ? lds_tw : (size_t)0) + 15) & ~(size_t)15;
     b->moved_off.resize(n);
     b->nctr = (int64_t)(sizeof(BatchCounters) / sizeof(unsigned long long));
     for (int i = 0; i < n; ++i) {
@@ -414,7 +424,8 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<-1>, kThreads, b->lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, b->tw_lds ? batch_kernel<-1, true> : batch_kernel<-1, false>, kThreads, b->lds);
     if (e != hipSuccess || per_cu < 1 || ncu < 1) {
         batch_free(b);
         return e != hipSuccess ? batch_fail_hip(e, "occupancy query") : fail(FFTRW_E_DEVICE, "kernel does not fit");

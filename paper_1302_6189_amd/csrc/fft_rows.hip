@@ -64,42 +64,46 @@ hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in,
     return hipGetLastError();
 }
 
-template <typename C, int DIR>
+template <typename C, int DIR, bool TW_LDS>
 __global__ void __launch_bounds__(kThreads)
     fft_xpose_generic_kernel(const C *in, C *out, FftDesc f, XposeDesc d, int rw, int G,
                              typename RealOf<C>::type scale, int do_scale)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    fft_xpose_unit<C, DIR>(in, out, f, d, rw, G, blockIdx.x, scale, do_scale != 0, smem_raw);
+    fft_xpose_unit<C, DIR, TW_LDS>(in, out, f, d, rw, G, blockIdx.x, scale, do_scale != 0, smem_raw);
 }
 
 // one FFT step of 2,3,5-smooth rows fused with the transpose that follows
 hipError_t launch_fft_xpose_generic(const FftDesc &f, const XposeDesc &d, bool fp64, int dir, const void *in,
                                     void *out, double scale, hipStream_t s)
 {
+    const size_t esz = fp64 ? 16 : 8;
     int rw = 1, G = 1;
-    fused_unit_shape(f.N, fp64 ? 16 : 8, d.Nv, d.nslices, fp64 ? 2048 : 4096, &rw, &G);
+    fused_unit_shape(f.N, esz, d.Nv, d.nslices, fp64 ? 2048 : 4096, &rw, &G);
     const int64_t nblk = ((d.Nv + rw - 1) / rw) * ((d.nslices + G - 1) / G);
     if (nblk <= 0) return hipSuccess;
     if (nblk >= (int64_t)0x7fffffff) return hipErrorInvalidValue;
-    const size_t lds = fused_unit_bytes(f.N, rw, G, fp64 ? 16 : 8);
+    const bool tw = unit_tw_fits(f.N, esz);
+    const size_t lds = fused_unit_bytes(f.N, rw, G, esz, tw);
     const int do_scale = scale != 1.0;
     dim3 grid((unsigned)nblk), block(kThreads);
+#define FFTRW_LAUNCH(C, D, T, SC)                                                                             \
+    hipLaunchKernelGGL((fft_xpose_generic_kernel<C, D, T>), grid, block, lds, s, (const C *)in, (C *)out, f, d, \
+                       rw, G, SC, do_scale)
     if (fp64) {
-        if (dir < 0)
-            hipLaunchKernelGGL((fft_xpose_generic_kernel<double2, -1>), grid, block, lds, s, (const double2 *)in,
-                               (double2 *)out, f, d, rw, G, scale, do_scale);
-        else
-            hipLaunchKernelGGL((fft_xpose_generic_kernel<double2, 1>), grid, block, lds, s, (const double2 *)in,
-                               (double2 *)out, f, d, rw, G, scale, do_scale);
+        if (dir < 0) {
+            if (tw) FFTRW_LAUNCH(double2, -1, true, scale); else FFTRW_LAUNCH(double2, -1, false, scale);
+        } else {
+            if (tw) FFTRW_LAUNCH(double2, 1, true, scale); else FFTRW_LAUNCH(double2, 1, false, scale);
+        }
     } else {
-        if (dir < 0)
-            hipLaunchKernelGGL((fft_xpose_generic_kernel<float2, -1>), grid, block, lds, s, (const float2 *)in,
-                               (float2 *)out, f, d, rw, G, (float)scale, do_scale);
-        else
-            hipLaunchKernelGGL((fft_xpose_generic_kernel<float2, 1>), grid, block, lds, s, (const float2 *)in,
-                               (float2 *)out, f, d, rw, G, (float)scale, do_scale);
+        if (dir < 0) {
+            if (tw) FFTRW_LAUNCH(float2, -1, true, (float)scale); else FFTRW_LAUNCH(float2, -1, false, (float)scale);
+        } else {
+            if (tw) FFTRW_LAUNCH(float2, 1, true, (float)scale); else FFTRW_LAUNCH(float2, 1, false, (float)scale);
+        }
     }
+#undef FFTRW_LAUNCH
     return hipGetLastError();
 }
 

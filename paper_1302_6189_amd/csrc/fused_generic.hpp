@@ -6,8 +6,9 @@
 // the next layout B) in each of G consecutive batch slices (G > 1 when the
 // rows are short): each row is contiguous along u
 // (the FFT axis), rows sit a_sv apart.  The rows are staged in LDS (row pitch
-// N + 1, or N + 2 for even complex64 rows, see unit_pitch), transformed by the same
-// Stockham passes as fft_rows_block, and written in layout B: for every
+// N + 1, or N + 2 for even complex64 rows, see unit_pitch), with the twiddle
+// table when it is small, transformed by the same Stockham passes as
+// fft_rows_block, and written in layout B: for every
 // frequency k the RW results form one run of consecutive v.  One HBM round trip
 // replaces two (the FFT step's and the transpose's).  Owner changes are counted
 // per row as in the transpose tile (tile_moved).
@@ -45,10 +46,18 @@ inline void fused_unit_shape(int N, size_t esz, int64_t Nv, int64_t nslices, int
     *G = g;
 }
 
-// LDS bytes of a fused unit: G * RW padded rows, the slices' bases, one int
-__host__ __device__ inline size_t fused_unit_bytes(int N, int rw, int G, size_t esz)
+// Units may stage the row length's twiddle table in LDS when its N entries
+// take at most 16 KB (the passes then read it there instead of through the
+// caches); longer rows keep the unit within 64 KB of LDS.
+constexpr size_t kUnitTwLds = 16384;
+__host__ __device__ inline bool unit_tw_fits(int N, size_t esz) { return (size_t)N * esz <= kUnitTwLds; }
+
+// LDS bytes of a fused unit: G * RW padded rows, the twiddle table when
+// staged, the slices' bases, one int
+__host__ __device__ inline size_t fused_unit_bytes(int N, int rw, int G, size_t esz, bool tw_lds)
 {
-    return (((size_t)G * rw * unit_pitch(N, esz) * esz + 15) & ~(size_t)15) + (size_t)G * 16 + 16;
+    return (((size_t)G * rw * unit_pitch(N, esz) * esz + 15) & ~(size_t)15) +
+           (tw_lds ? (((size_t)N * esz + 15) & ~(size_t)15) : 0) + (size_t)G * 16 + 16;
 }
 
 // Rows (slice g0 + gi, v0 + r) of a unit into LDS (row rho = gi rw + r at
@@ -162,7 +171,9 @@ __device__ __forceinline__ void store_unit_runs(C *__restrict__ out, const C *ld
 }
 
 // Unit `unit` of a fused step: v-block unit % tiles_v of G consecutive slices.
-template <typename C, int DIR>
+// TW_LDS: the twiddle table is staged in LDS (the caller checked unit_tw_fits
+// and sized the LDS block with it).
+template <typename C, int DIR, bool TW_LDS>
 __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__restrict__ out, const FftDesc &f,
                                                const XposeDesc &d, int rw, int G, int64_t unit,
                                                typename RealOf<C>::type scale, bool do_scale, unsigned char *smem)
@@ -171,7 +182,9 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
     const int S = unit_pitch(N, sizeof(C));
     C *lds = reinterpret_cast<C *>(smem);
     const size_t rows_bytes = ((size_t)G * rw * S * sizeof(C) + 15) & ~(size_t)15;
-    int64_t *abase = reinterpret_cast<int64_t *>(smem + rows_bytes);
+    C *ltw = reinterpret_cast<C *>(smem + rows_bytes);
+    const size_t tw_bytes = TW_LDS ? (((size_t)N * sizeof(C) + 15) & ~(size_t)15) : 0;
+    int64_t *abase = reinterpret_cast<int64_t *>(smem + rows_bytes + tw_bytes);
     int64_t *bbase = abase + G;
     const int64_t tiles_v = (d.Nv + rw - 1) / rw;
     const int64_t tv = unit % tiles_v;
@@ -197,6 +210,10 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
     } else {
         load_unit_rows<1>(in, lds, f, d, abase, S, rw, nv, ng, g0, v0, moved);
     }
+    if constexpr (TW_LDS) {
+        const C *gtw = reinterpret_cast<const C *>(f.tw);
+        for (int i = threadIdx.x; i < N; i += kThreads) ltw[i] = gtw[i];
+    }
     if (d.count) {
         // each wave publishes its sum at once: work left for the end of the
         // unit would delay the group's next unit or its exit
@@ -209,7 +226,7 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
     const int row = threadIdx.x / lanes;
     const int lane = threadIdx.x - row * lanes;
     C *lrow = lds + row * S;
-    const C *tw = reinterpret_cast<const C *>(f.tw);
+    const C *tw = TW_LDS ? static_cast<const C *>(ltw) : reinterpret_cast<const C *>(f.tw);
     int Ns = 1;
     for (int p = 0; p < f.npass; ++p) {
         switch (f.radix[p]) {
