@@ -129,7 +129,9 @@ __device__ __forceinline__ void store_block(C *__restrict__ dst, const C *lds, i
 }
 
 // One work-group's share of a batched row FFT: rows [blk * RW, blk * RW + RW).
-template <typename C, int DIR>
+// TW_LDS: the N-entry twiddle table is staged in LDS after the rows (the
+// caller sized the block for it), so the passes read it there.
+template <typename C, int DIR, bool TW_LDS = false>
 __device__ __forceinline__ void fft_rows_block(const C *in, C *out, const FftDesc &d, int64_t blk,
                                                typename RealOf<C>::type scale, bool do_scale, C *lds)
 {
@@ -139,12 +141,17 @@ __device__ __forceinline__ void fft_rows_block(const C *in, C *out, const FftDes
     const int rows_here = left < d.rows_per_wg ? (int)left : d.rows_per_wg;
     const int cnt = rows_here * N;
     load_block(lds, in + row0 * N, cnt);
+    C *ltw = lds + (int64_t)d.rows_per_wg * N;
+    if constexpr (TW_LDS) {
+        const C *gtw = reinterpret_cast<const C *>(d.tw);
+        for (int i = threadIdx.x; i < N; i += kThreads) ltw[i] = gtw[i];
+    }
     __syncthreads();
     const int lanes = d.lanes_per_row;
     const int row = threadIdx.x / lanes;
     const int lane = threadIdx.x - row * lanes;
     C *lrow = lds + row * N;
-    const C *tw = reinterpret_cast<const C *>(d.tw);
+    const C *tw = TW_LDS ? static_cast<const C *>(ltw) : reinterpret_cast<const C *>(d.tw);
     int Ns = 1;
     for (int p = 0; p < d.npass; ++p) {
         switch (d.radix[p]) {

@@ -29,12 +29,12 @@ hipError_t launch_twiddles(void *out, int64_t n, bool fp64, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename C, int DIR>
+template <typename C, int DIR, bool TW_LDS>
 __global__ void __launch_bounds__(kThreads)
     fft_rows_kernel(const C *in, C *out, FftDesc d, typename RealOf<C>::type scale, int do_scale)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    fft_rows_block<C, DIR>(in, out, d, blockIdx.x, scale, do_scale != 0, reinterpret_cast<C *>(smem_raw));
+    fft_rows_block<C, DIR, TW_LDS>(in, out, d, blockIdx.x, scale, do_scale != 0, reinterpret_cast<C *>(smem_raw));
 }
 
 hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in, void *out, double scale,
@@ -43,24 +43,27 @@ hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in,
     const int64_t nblk = (d.nrows + d.rows_per_wg - 1) / d.rows_per_wg;
     if (nblk <= 0) return hipSuccess;
     const size_t esz = fp64 ? 16 : 8;
-    const size_t lds = (size_t)d.rows_per_wg * d.N * esz;
+    // the twiddle table goes to LDS after the rows when it takes at most 16 KB
+    const bool tw = unit_tw_fits(d.N, esz);
+    const size_t lds = ((size_t)d.rows_per_wg * d.N + (tw ? d.N : 0)) * esz;
     const int do_scale = scale != 1.0;
     dim3 grid((unsigned)nblk), block(kThreads);
+#define FFTRW_LAUNCH(C, D, T, SC) \
+    hipLaunchKernelGGL((fft_rows_kernel<C, D, T>), grid, block, lds, s, (const C *)in, (C *)out, d, SC, do_scale)
     if (fp64) {
-        if (dir < 0)
-            hipLaunchKernelGGL((fft_rows_kernel<double2, -1>), grid, block, lds, s, (const double2 *)in,
-                               (double2 *)out, d, scale, do_scale);
-        else
-            hipLaunchKernelGGL((fft_rows_kernel<double2, 1>), grid, block, lds, s, (const double2 *)in,
-                               (double2 *)out, d, scale, do_scale);
+        if (dir < 0) {
+            if (tw) FFTRW_LAUNCH(double2, -1, true, scale); else FFTRW_LAUNCH(double2, -1, false, scale);
+        } else {
+            if (tw) FFTRW_LAUNCH(double2, 1, true, scale); else FFTRW_LAUNCH(double2, 1, false, scale);
+        }
     } else {
-        if (dir < 0)
-            hipLaunchKernelGGL((fft_rows_kernel<float2, -1>), grid, block, lds, s, (const float2 *)in,
-                               (float2 *)out, d, (float)scale, do_scale);
-        else
-            hipLaunchKernelGGL((fft_rows_kernel<float2, 1>), grid, block, lds, s, (const float2 *)in,
-                               (float2 *)out, d, (float)scale, do_scale);
+        if (dir < 0) {
+            if (tw) FFTRW_LAUNCH(float2, -1, true, (float)scale); else FFTRW_LAUNCH(float2, -1, false, (float)scale);
+        } else {
+            if (tw) FFTRW_LAUNCH(float2, 1, true, (float)scale); else FFTRW_LAUNCH(float2, 1, false, (float)scale);
+        }
     }
+#undef FFTRW_LAUNCH
     return hipGetLastError();
 }
 
