@@ -88,11 +88,17 @@ enum {
                                         owner changes in every transpose          */
     FFTRW_FLAG_OWN_MATCHED = 8u,     /* ownership reading R2 (see fft_comm_volume)*/
     FFTRW_FLAG_FUSED_FFT = 16u,      /* fuse each FFT step with the transpose that
-                                        follows it (one HBM pass per step)        */
+                                        follows it (one HBM pass per step).  The
+                                        default: a plan fuses whenever every step
+                                        qualifies (see fft_plan); the flag only
+                                        states it                                 */
     FFTRW_FLAG_BATCH_NO_GRAPH = 32u, /* batched form: launch the persistent kernel
                                         directly instead of replaying a graph     */
-    FFTRW_FLAG_BATCH_NO_FUSE = 64u   /* batched form: separate FFT and transpose
+    FFTRW_FLAG_BATCH_NO_FUSE = 64u,  /* batched form: separate FFT and transpose
                                         stages (allows in == out)                 */
+    FFTRW_FLAG_SEPARATE = 128u       /* plans: run every FFT step and every
+                                        transpose as kernels of their own (two HBM
+                                        passes per step); excludes FUSED_FFT      */
 };
 
 typedef struct fft_plan_s *fft_plan_t;
@@ -143,7 +149,9 @@ int fft_comm_volume(int M, const int64_t *dims, int64_t P, const int8_t *order,
  * processes runs ceil(log2 c) butterfly stages whose partners sit on other
  * processes, each sending every point of the row once, so the row adds
  * N * ceil(log2 c) points.  With it the 64^3 comparison of Section 4 against
- * the 3-D method (Eq. (23)) peaks at 8,192 processes at 11.6 times.
+ * the 3-D method (Eq. (23)) peaks at 8,192 processes at 11.6 times.  This
+ * reading was chosen because it reproduces that printed 11.6: it is fitted
+ * to the one number it is checked against, so its parity is unpinned.
  *   per_step[M] (nullable): one count per FFT step t = 1..M (0 below level M).
  *   total: their sum.
  * Errors: FFTRW_E_ARG, FFTRW_E_SIZE, FFTRW_E_ORDER, FFTRW_E_ROWSPLIT if P > T.
@@ -232,6 +240,14 @@ int fft_compare_models(double N, double P, double *out);
  * along the FFT axis) run: the processes sharing a row share device memory,
  * so the row is transformed whole, and the transposes are counted exactly as
  * at other levels; staged transposes refuse them (FFTRW_E_ROWSPLIT).
+ * Fusion: unless flags hold FFTRW_FLAG_SEPARATE or FFTRW_FLAG_STAGED, each
+ * FFT step runs fused with the transpose that follows it when every step
+ * qualifies (power-of-two rows of 16..512 points for C64, 16..256 for C128,
+ * whose work-group's run along the next layout's last axis fits that axis;
+ * other 2,3,5-smooth rows up to 4095 points for C64, 2047 for C128; 256-point
+ * rows of the split MFMA forms); otherwise, and for execs with in == out, the
+ * steps and transposes run as separate kernels.  Results are bit-identical
+ * either way; fft_plan_describe's text starts with "fused|" when it fuses.
  * The plan owns its device workspace (fft_workspace_bytes) and twiddle
  * tables; it must outlive every exec enqueued with it.  One exec per plan may
  * be in flight at a time.
@@ -302,8 +318,8 @@ int fft_plan_set_timing(fft_plan_t plan, int enable);
  * exec with timing enabled, in launch order: FFT step 1, transpose 1, FFT
  * step 2, ..., FFT step M, return transpose (absent with LEAVE_PERMUTED).
  * With FFTRW_FLAG_STAGED each transpose is three stages: pack, exchange,
- * unpack.  With FFTRW_FLAG_FUSED_FFT (when the plan fuses) each stage is one
- * FFT step together with the transpose that follows it.
+ * unpack.  When the plan fuses (see fft_plan) each stage is one FFT step
+ * together with the transpose that follows it.
  * ms: host array of capacity `cap`; *n receives the number of stages.
  * Synchronises on the last event.
  */

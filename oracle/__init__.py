@@ -19,5 +19,9 @@ Parity status: every function is pinned by a test against values the paper
 prints, closed forms, textbook identities or brute force.  The row-split
 regime (level M) follows a stated reading in ``pipeline`` (a split row is
 transformed whole); its values are pinned by the M-D DFT, its amounts by the
-closed form at N_p = T (every point its own process).
+closed form at N_p = T (every point its own process).  One function is
+parity unpinned: ``decomp.split_row_volume``, the points a split row's own
+1-D FFT would exchange under the binary-exchange reading, which was fitted to
+the 11.6 of Section 4 and is checked only against that number and its own
+reading.
 """

@@ -189,7 +189,11 @@ def split_row_volume(dims, P: int, perm) -> int:
     that decomposition is at level M, under the binary-exchange reading (the
     paper does not say how a split row is transformed): a row held by c > 1
     processes runs ceil(log2 c) butterfly stages across processes, each
-    sending all N points of the row.  0 below level M."""
+    sending all N points of the row.  0 below level M.
+
+    Parity unpinned: this reading was chosen because it reproduces the 11.6
+    printed for the 64^3 comparison with the 3-D method in Section 4, so that
+    check confirms the choice rather than the function."""
     pdims = [int(dims[a]) for a in perm]
     M = len(pdims)
     if level(pdims, P) < M:

@@ -5,13 +5,20 @@
 // units -- a block of rows of one FFT step, or a tile of one transpose --
 // grouped into stage levels: level s holds stage s of every item that has
 // one.  One grid of work-groups, sized to stay resident, sweeps the levels:
-// inside a level units are taken from the level's atomic counter; between
-// levels the grid meets at a barrier (one release before arriving, one
-// acquire after leaving, at device scope, so the data written on one XCD is
-// seen on the others), which keeps every item's FFT -> transpose -> FFT order.
-// Waiting polls a device-coherent counter without invalidating caches, and
-// every wait is bounded by the real-time clock: past the bound the
-// work-group sets an error flag and goes on, so the grid always drains.
+// inside a level units are taken from the level's atomic counter.  A
+// work-group leaving a level adds the number of units it completed there to
+// the level's done counter (after a release at device scope) and waits until
+// the counter holds every unit of the level (then acquires, so data written
+// on one XCD is seen on the others), which keeps every item's FFT ->
+// transpose -> FFT order.  Counting units rather than arrivals means no
+// work-group waits for one that has not started: a unit is only ever claimed
+// by a running work-group, and a level is left only once all its units are
+// claimed, so the wait ends whether or not the whole grid is resident
+// (another kernel may hold part of the device).  Waiting polls a
+// device-coherent counter without invalidating caches, and every wait is
+// bounded by the real-time clock: past the bound the work-group adds one to
+// a sticky time-out count and goes on, so the grid always drains and the
+// host can refuse the result.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,11 +64,10 @@ struct BatchTask {
     int64_t unit0, nunits;  // unit0 counts from the start of the task's level
 };
 
-// zeroed before every launch: error flag, barrier arrivals, one unit counter per level
+// zeroed before every launch: one claim counter and one done counter per level
 struct BatchCounters {
-    unsigned long long error;
-    unsigned long long arrived;
     unsigned long long next[kMaxStages];
+    unsigned long long done[kMaxStages];
 };
 
 // task starts of one level held in LDS for the per-unit search
@@ -79,7 +85,7 @@ template <int DIR, bool TW_LDS>
 __global__ void __launch_bounds__(kThreads)
     batch_kernel(const BatchItemDev *__restrict__ items, const BatchTask *__restrict__ tasks,
                  const int *__restrict__ level_task0, const int64_t *__restrict__ level_units, int nlevels,
-                 BatchCounters *ctr)
+                 BatchCounters *ctr, unsigned long long *timeouts)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t s_unit0[kLevelTasksLds];
@@ -96,13 +102,14 @@ __global__ void __launch_bounds__(kThreads)
         // thread 0 claims units from the level's counter -- the next claim is
         // issued before the current unit runs, hiding its latency -- finds the
         // unit's task and hands both to the work-group
-        unsigned long long next = 0;
+        unsigned long long next = 0, ndone = 0;
         if (threadIdx.x == 0) next = atomicAdd(&ctr->next[lv], 1ull);
         for (;;) {
             if (threadIdx.x == 0) {
                 const int64_t u = (int64_t)next;
                 int lo = 0;
                 if (u < nunits) {
+                    ++ndone;
                     next = atomicAdd(&ctr->next[lv], 1ull);
                     int hi = t1 - t0 - 1;
                     while (lo < hi) {
@@ -153,16 +160,16 @@ __global__ void __launch_bounds__(kThreads)
             }
         }
         if (lv + 1 == nlevels) break;
-        // grid barrier between levels
+        // level barrier: publish the units this group completed, wait for all
         __threadfence();  // release this work-group's writes of the level
         __syncthreads();
         if (threadIdx.x == 0) {
-            const unsigned long long target = (unsigned long long)gridDim.x * (unsigned long long)(lv + 1);
-            atomicAdd(&ctr->arrived, 1ull);
+            const unsigned long long target = (unsigned long long)nunits;
+            if (ndone) atomicAdd(&ctr->done[lv], ndone);
             const unsigned long long w0 = wall_clock64();
-            while (__hip_atomic_load(&ctr->arrived, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            while (__hip_atomic_load(&ctr->done[lv], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 if (wall_clock64() - w0 > kWaitTicks) {
-                    atomicOr(&ctr->error, 1ull);
+                    atomicAdd(timeouts, 1ull);
                     break;
                 }
                 __builtin_amdgcn_s_sleep(10);
@@ -197,6 +204,8 @@ struct fft_batch_impl {
     BatchItemDev *d_items = nullptr;
     BatchTask *d_tasks = nullptr;
     unsigned long long *d_ctr = nullptr;  // BatchCounters, then moved[sum of M_i]
+    unsigned long long *d_timeouts = nullptr;  // sticky count of timed-out waits (never reset)
+    bool timed_out = false;               // a stats call has seen d_timeouts != 0
     int64_t nctr = 0;
     std::vector<int> level_task0;         // first task of each level (+ end)
     std::vector<int64_t> level_units;     // units of each level
@@ -231,7 +240,7 @@ void batch_free(fft_batch_impl *b)
     }
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     for (void *p : {(void *)b->d_items, (void *)b->d_tasks, (void *)b->d_ctr, (void *)b->d_level_task0,
-                    (void *)b->d_level_units})
+                    (void *)b->d_level_units, (void *)b->d_timeouts})
         if (p) (void)hipFree(p);
     for (fft_plan_t p : b->plans) plan_free(p);
     delete b;
@@ -248,7 +257,7 @@ int batch_enqueue(fft_batch_impl *b, int dir, hipStream_t s)
     const int nl = (int)b->level_units.size();
 #define FFTRW_LAUNCH(D, T)                                                                                   \
     hipLaunchKernelGGL((batch_kernel<D, T>), dim3(b->grid), dim3(kThreads), b->lds, s, b->d_items, b->d_tasks, \
-                       b->d_level_task0, b->d_level_units, nl, ctr)
+                       b->d_level_task0, b->d_level_units, nl, ctr, b->d_timeouts)
     if (dir < 0) {
         if (b->tw_lds) FFTRW_LAUNCH(-1, true); else FFTRW_LAUNCH(-1, false);
     } else {
@@ -434,6 +443,8 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
     e = hipMalloc(&b->d_items, sizeof(BatchItemDev) * (size_t)n);
     if (e == hipSuccess) e = hipMalloc(&b->d_tasks, sizeof(BatchTask) * b->h_tasks.size());
     if (e == hipSuccess) e = hipMalloc(&b->d_ctr, sizeof(unsigned long long) * (size_t)b->nctr);
+    if (e == hipSuccess) e = hipMalloc(&b->d_timeouts, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(b->d_timeouts, 0, sizeof(unsigned long long));
     if (e == hipSuccess && (flags & FFTRW_FLAG_COUNT_MOVED)) {
         // owner-change counters of every transpose live in the batch's counter
         // block, which the graph's reset kernel clears before each launch
@@ -472,6 +483,8 @@ static int batch_exec(fft_batch_t b, void *const *in, void *const *out, void *st
 {
     g_last_error.clear();
     if (!b || !in || !out) return fail(FFTRW_E_ARG, "null batch or pointer arrays");
+    if (b->timed_out)
+        return fail(FFTRW_E_DEVICE, "an earlier launch of this batch timed out at a level barrier");
     bool changed = !b->pointers_set;
     for (int i = 0; i < b->n; ++i) {
         if (!in[i] || !out[i]) return fail(FFTRW_E_ARG, "null buffer for item " + std::to_string(i));
@@ -525,10 +538,12 @@ int fft_batch_stats(fft_batch_t b, int64_t *moved, int64_t *analytic, int64_t *u
     if (!b) return fail(FFTRW_E_ARG, "null batch");
     if (units) *units = b->total;
     std::vector<unsigned long long> h((size_t)b->nctr, 0ull);
-    if (moved || error) {
+    unsigned long long timeouts = 0;
+    {
         hipError_t e = hipDeviceSynchronize();
-        if (e == hipSuccess) e = hipMemcpy(h.data(), b->d_ctr, sizeof(unsigned long long) * h.size(),
-                                           hipMemcpyDeviceToHost);
+        if (e == hipSuccess && moved)
+            e = hipMemcpy(h.data(), b->d_ctr, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(&timeouts, b->d_timeouts, sizeof(timeouts), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return batch_fail_hip(e, "reading batch counters");
     }
     const bool leave = (b->flags & FFTRW_FLAG_LEAVE_PERMUTED) != 0;
@@ -550,7 +565,12 @@ int fft_batch_stats(fft_batch_t b, int64_t *moved, int64_t *analytic, int64_t *u
         }
         off += M;
     }
-    if (error) *error = (int)h[0];
+    if (error) *error = (int)std::min<unsigned long long>(timeouts, 0x7fffffffull);
+    if (timeouts) {
+        b->timed_out = true;
+        return fail(FFTRW_E_DEVICE, std::to_string(timeouts) +
+                                        " level-barrier wait(s) timed out; results of this batch are unreliable");
+    }
     return FFTRW_OK;
 }
 

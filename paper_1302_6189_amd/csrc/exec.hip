@@ -378,8 +378,11 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
     if (precision != FFTRW_PREC_NATIVE && dtype != FFTRW_C64)
         return fail(FFTRW_E_UNSUPPORTED, "the split-precision MFMA form computes complex64 data");
     if (flags & ~(unsigned)(FFTRW_FLAG_LEAVE_PERMUTED | FFTRW_FLAG_STAGED | FFTRW_FLAG_COUNT_MOVED |
-                            FFTRW_FLAG_OWN_MATCHED | FFTRW_FLAG_FUSED_FFT | FFTRW_FLAG_BATCH_NO_GRAPH))
+                            FFTRW_FLAG_OWN_MATCHED | FFTRW_FLAG_FUSED_FFT | FFTRW_FLAG_BATCH_NO_GRAPH |
+                            FFTRW_FLAG_SEPARATE))
         return fail(FFTRW_E_ARG, "unknown flag bits");
+    if ((flags & FFTRW_FLAG_SEPARATE) && (flags & FFTRW_FLAG_FUSED_FFT))
+        return fail(FFTRW_E_ARG, "FFTRW_FLAG_SEPARATE and FFTRW_FLAG_FUSED_FFT exclude each other");
 
     fft_plan_s *pl = new (std::nothrow) fft_plan_s();
     if (!pl) return fail(FFTRW_E_NOMEM, "out of host memory");
@@ -506,11 +509,12 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
             }
         }
     }
-    // fusion of every FFT step with its transpose: power-of-two rows of 16..512
-    // (256 in FP64) whose work-group's run of consecutive v-values fits the v
-    // axis use the compile-time kernel; 2,3,5-smooth rows use the generic unit;
-    // steps of the split-precision form (256 points) use the MFMA kernel
-    if ((flags & FFTRW_FLAG_FUSED_FFT) && !(flags & FFTRW_FLAG_STAGED) && !generic_rows) {
+    // fusion of every FFT step with its transpose (the default): power-of-two
+    // rows of 16..512 (256 in FP64) whose work-group's run of consecutive
+    // v-values fits the v axis use the compile-time kernel; 2,3,5-smooth rows
+    // use the generic unit; steps of the split-precision form (256 points) use
+    // the MFMA kernel
+    if (!(flags & (FFTRW_FLAG_SEPARATE | FFTRW_FLAG_STAGED)) && !generic_rows) {
         const bool fp64 = pl->esz == 16;
         const int nx = (flags & FFTRW_FLAG_LEAVE_PERMUTED) ? M - 1 : M;
         bool ok = true;

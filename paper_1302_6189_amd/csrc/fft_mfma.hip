@@ -357,9 +357,12 @@ __global__ void __launch_bounds__(kThreads)
             wave_sync();  // xb and yb are rewritten by the wave's next row
         }
         __syncthreads();
-        // runs of consecutive v for every k, two values per 16-byte store
+        // runs of consecutive v for every k, two values per 16-byte store when
+        // N_v is even (every other stride of layout B is then a multiple of
+        // N_v, so pairs start 16 bytes aligned); 8-byte stores otherwise
         constexpr int HP = kMfmaRows / 2;
         const int npair = (nv + 1) / 2;
+        const bool wide = (d.Nv & 1) == 0;
         float2 *dstb = out + bbase + v0;
         for (int idx = threadIdx.x; idx < 256 * HP; idx += kThreads) {
             const int rp = idx % HP;
@@ -368,12 +371,13 @@ __global__ void __launch_bounds__(kThreads)
             const int r0 = 2 * rp;
             float2 *p = dstb + (int64_t)k * d.b_su + r0;
             const float2 a0 = stg[k * SR + r0];
-            if (r0 + 1 < nv) {
+            if (r0 + 1 < nv && wide) {
                 const float2 a1v = stg[k * SR + r0 + 1];
                 mf4v w = {a0.x, a0.y, a1v.x, a1v.y};
                 __builtin_nontemporal_store(w, reinterpret_cast<mf4v *>(p));
             } else {
                 xst(p, a0);
+                if (r0 + 1 < nv) xst(p + 1, stg[k * SR + r0 + 1]);
             }
         }
         __syncthreads();  // the staging block is refilled by the next unit

@@ -322,9 +322,12 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
             }
     }
     __syncthreads();
-    // runs of consecutive v for every k, two values per 16-byte store
+    // runs of consecutive v for every k, two values per 16-byte store when
+    // N_v is even: every stride of layout B other than v's is then a multiple
+    // of N_v, so each pair starts 16 bytes aligned (odd N_v: 8-byte stores)
     constexpr int HP = RW / 2;
     const int npair = (nv + 1) / 2;
+    const bool wide = (d.Nv & 1) == 0;
     C *dstb = out + bbase + v0;
     for (int idx = threadIdx.x; idx < N * HP; idx += NT) {
         const int rp = idx % HP;
@@ -336,9 +339,14 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
         if (r0 + 1 < nv) {
             const C a1 = lds[k * SROW + r0 + 1];
             if constexpr (sizeof(C) == 8) {
-                using V4 = typename Vec2<float2>::type;
-                V4 w = {a0.x, a0.y, a1.x, a1.y};
-                __builtin_nontemporal_store(w, reinterpret_cast<V4 *>(p));
+                if (wide) {
+                    using V4 = typename Vec2<float2>::type;
+                    V4 w = {a0.x, a0.y, a1.x, a1.y};
+                    __builtin_nontemporal_store(w, reinterpret_cast<V4 *>(p));
+                } else {
+                    st_nt(p, a0);
+                    st_nt(p + 1, a1);
+                }
             } else {
                 st_nt(p, a0);
                 st_nt(p + 1, a1);

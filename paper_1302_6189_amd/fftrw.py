@@ -27,6 +27,7 @@ OWN_LITERAL, OWN_MATCHED = 0, 1
 FLAG_LEAVE_PERMUTED, FLAG_STAGED, FLAG_COUNT_MOVED, FLAG_OWN_MATCHED, FLAG_FUSED_FFT = 1, 2, 4, 8, 16
 FLAG_BATCH_NO_GRAPH = 32
 FLAG_BATCH_NO_FUSE = 64
+FLAG_SEPARATE = 128
 
 LETTERS = "abcdefgh"
 

@@ -79,8 +79,9 @@ def batch_items(n_items: int = 256, seed: int = 5, max_points: int = 1 << 22):
     """List of (dims, P) for the batched workload.
 
     M ~ U{3, 4, 5}; each size ~ U over SMOOTH_SIZES; an item whose point count
-    exceeds ``max_points`` is redrawn; P ~ U{1..64}, capped so that the
-    decomposition never has to split rows along the transformed axis.
+    exceeds ``max_points`` is redrawn; P ~ U{1..64}, not capped.  (With every
+    size >= 12 and M >= 3 an item has at least 144 rows along any axis, so
+    P <= 64 never reaches the row-split level M of Eq. (13).)
     """
     g = rng(seed)
     items = []

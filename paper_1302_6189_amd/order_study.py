@@ -28,7 +28,7 @@ import numpy as np
 
 from . import fftrw
 
-MODES = {"fused": fftrw.FLAG_FUSED_FFT, "separate": 0, "staged": fftrw.FLAG_STAGED}
+MODES = {"fused": fftrw.FLAG_FUSED_FFT, "separate": fftrw.FLAG_SEPARATE, "staged": fftrw.FLAG_STAGED}
 SEED = 13026189
 
 

@@ -81,19 +81,41 @@ def test_batch_matches_per_item_plans(gpu_lib):
         assert st["moved"][i] == st["analytic"][i]
 
 
-def test_full_256_item_batch(gpu_lib):
+@pytest.fixture(scope="module")
+def batch256():
+    """The 256-item batched workload (seed 13026189 + 5) run once in each
+    schedule: fused stages (the default) and separate FFT / transpose stages."""
     items = inputs.batch_items(256, seed=5)
     xs = [inputs.uniform(d, 1000 + i, np.complex64) for i, (d, _) in enumerate(items)]
-    b = fftrw.Batch(items, flags=fftrw.FLAG_COUNT_MOVED)
-    ins, outs = _run(b, xs)
-    st = b.stats()
-    assert st["error"] == 0
-    assert all(m == a for m, a in zip(st["moved"], st["analytic"]))
-    for i in (0, 7, 100, 255):
+    runs = {}
+    for name, extra in (("fused", 0), ("separate", fftrw.FLAG_BATCH_NO_FUSE)):
+        b = fftrw.Batch(items, flags=fftrw.FLAG_COUNT_MOVED | extra)
+        ins, outs = _run(b, xs)
+        st = b.stats()
+        runs[name] = ([to_host(o) for o in outs], st)
+        del ins, outs
+        b.destroy()
+    return items, xs, runs
+
+
+@pytest.mark.parametrize("chunk", range(8))
+def test_full_256_item_batch_against_oracle(gpu_lib, batch256, chunk):
+    # every item of the workload, both schedules: values against the FP64
+    # oracle element by element, device counts against the analytic amounts
+    items, xs, runs = batch256
+    for i in range(32 * chunk, 32 * chunk + 32):
         dims, P = items[i]
         order = fftrw.fft_order_search(dims, P)["best_order"]
         ref = dft.fftn_direct(xs[i], orders.fft_axis_sequence(order))
-        assert dft.rel_l2(to_host(outs[i]), ref) < 1e-5, (i, dims)
+        steps, _, ret = fftrw.fft_comm_volume(dims, P, order)
+        for name, (ys, st) in runs.items():
+            assert st["error"] == 0
+            y = ys[i]
+            err, mrel = dft.rel_l2(y, ref), dft.max_abs_rel(y, ref)
+            assert err < 1e-5 and mrel < 1e-5, (name, i, dims, P, err, mrel)
+            assert st["analytic"][i] == steps + [ret], (name, i)
+            assert st["moved"][i] == st["analytic"][i], (name, i, st["moved"][i])
+        assert np.array_equal(runs["fused"][0][i], runs["separate"][0][i]), i
 
 
 def test_autotuned_batch(gpu_lib, tmp_path):

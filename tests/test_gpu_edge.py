@@ -13,7 +13,7 @@ from tests.gpu_util import empty_dev, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-MODES = {"fused": fftrw.FLAG_FUSED_FFT, "separate": 0, "staged": fftrw.FLAG_STAGED}
+MODES = {"fused": fftrw.FLAG_FUSED_FFT, "separate": fftrw.FLAG_SEPARATE, "staged": fftrw.FLAG_STAGED}
 TOL = {np.complex64: 1e-5, np.complex128: 1e-12}
 DT = {np.complex64: fftrw.C64, np.complex128: fftrw.C128}
 

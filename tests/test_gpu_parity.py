@@ -256,7 +256,7 @@ def test_fused_fft_transpose(gpu_lib, dims, P, oidx, dtype):
         assert dft.rel_l2(to_host(yd), ref) < TOL[dtype]
     else:
         # full size: against the unfused pipeline (same kernels' arithmetic per row)
-        plain = fftrw.Plan(dims, P, order, dtype=DT[dtype])
+        plain = fftrw.Plan(dims, P, order, dtype=DT[dtype], flags=fftrw.FLAG_SEPARATE)
         zd = empty_dev(dims, dtype)
         plain.exec_fwd(xd, zd)
         assert np.array_equal(to_host(yd), to_host(zd))

@@ -18,7 +18,8 @@ from tests.gpu_util import empty_dev, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 PRECS = {"f16": (fftrw.PREC_SPLIT_F16, 3e-6), "bf16x3": (fftrw.PREC_SPLIT_BF16X3, 3e-6),
-         "bf16": (fftrw.PREC_SPLIT_BF16, 1e-4), "fp32": (fftrw.PREC_NATIVE, 1e-5)}
+         # two BF16 parts carry 16 bits: observed 7.8e-6 at 256^3, bound at about twice that
+         "bf16": (fftrw.PREC_SPLIT_BF16, 2e-5), "fp32": (fftrw.PREC_NATIVE, 1e-5)}
 
 
 @pytest.mark.parametrize("name", list(PRECS))
@@ -49,13 +50,16 @@ def cube256():
     return order, out
 
 
+@pytest.mark.parametrize("mode", ["fused", "separate"])
 @pytest.mark.parametrize("name", list(PRECS))
 @pytest.mark.parametrize("kind", ["uniform", "log_uniform"])
-def test_256cube_precision_forms(gpu_lib, cube256, name, kind):
+def test_256cube_precision_forms(gpu_lib, cube256, name, kind, mode):
     prec, tol = PRECS[name]
     order, data = cube256
     x, ref = data[kind]
-    plan = fftrw.Plan((256,) * 3, 64, order, precision=prec, flags=fftrw.FLAG_COUNT_MOVED)
+    extra = fftrw.FLAG_FUSED_FFT if mode == "fused" else fftrw.FLAG_SEPARATE
+    plan = fftrw.Plan((256,) * 3, 64, order, precision=prec, flags=fftrw.FLAG_COUNT_MOVED | extra)
+    assert plan.describe()[1].startswith("fused|") == (mode == "fused")
     xd = to_dev(x)
     yd = empty_dev(x.shape, np.complex64)
     plan.exec_fwd(xd, yd)
@@ -74,7 +78,7 @@ def test_256cube_precision_forms(gpu_lib, cube256, name, kind):
 
 @pytest.mark.parametrize("name", ["f16", "bf16", "bf16x3"])
 @pytest.mark.parametrize("dims,P,oidx", [((256, 256, 256), 64, 0), ((256, 40, 256), 7, 3),
-                                         ((256, 256, 24, 256), 300, 700)])
+                                         ((256, 256, 24, 256), 300, 700), ((256, 27, 256), 5, 0)])
 def test_fused_mfma_matches_separate_steps(gpu_lib, name, dims, P, oidx):
     # the 256-point MFMA transform fused with the transpose that follows runs the
     # same per-row arithmetic as the separate MFMA step; N_v = 40 and 24 leave
@@ -84,7 +88,7 @@ def test_fused_mfma_matches_separate_steps(gpu_lib, name, dims, P, oidx):
     x = inputs.uniform(dims, 44, np.complex64)
     xd = to_dev(x)
     fused = fftrw.Plan(dims, P, order, precision=prec, flags=fftrw.FLAG_FUSED_FFT | fftrw.FLAG_COUNT_MOVED)
-    plain = fftrw.Plan(dims, P, order, precision=prec, flags=fftrw.FLAG_COUNT_MOVED)
+    plain = fftrw.Plan(dims, P, order, precision=prec, flags=fftrw.FLAG_COUNT_MOVED | fftrw.FLAG_SEPARATE)
     desc = fused.describe()[1]
     assert desc.startswith("fused|") and "mfma:" in desc, desc
     for fwd in (True, False):
@@ -94,3 +98,7 @@ def test_fused_mfma_matches_separate_steps(gpu_lib, name, dims, P, oidx):
         assert np.array_equal(to_host(a), to_host(b)), fwd
         an, mv = fused.stats()
         assert mv == an
+        if fwd and np.prod(dims) <= 1 << 22:
+            # odd (27) and ragged (40) next-layout axes: against the oracle too
+            ref = dft.fftn_direct(x, orders.fft_axis_sequence(order))
+            assert dft.rel_l2(to_host(a), ref) < PRECS[name][1], name

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 DT = {np.complex64: fftrw.C64, np.complex128: fftrw.C128}
 TOL = {np.complex64: 1e-5, np.complex128: 1e-12}
-MODES = {"separate": 0, "fused": fftrw.FLAG_FUSED_FFT}
+MODES = {"separate": fftrw.FLAG_SEPARATE, "fused": fftrw.FLAG_FUSED_FFT}
 
 CASES = [((32, 32, 32), 2048, 3), ((64, 64, 64), 8192, 0), ((16, 8, 4), 100, 5), ((8, 8, 8), 512, 2),
          ((8, 8, 8, 8), 1000, 700), ((4, 4, 4, 4, 4), 300, 4000000), ((12, 10, 9), 500, 1),
@@ -56,7 +56,7 @@ def test_row_split_plans(gpu_lib, dims, P, oidx, dtype, mode):
         # plan of the same order at N_p = 8 (N_p changes no arithmetic)
         steps, _, ret = fftrw.fft_comm_volume(dims, P, order, allow_rowsplit=True)
         assert analytic == steps + [ret]
-        plain = fftrw.Plan(dims, 8, order, dtype=DT[dtype])
+        plain = fftrw.Plan(dims, 8, order, dtype=DT[dtype], flags=fftrw.FLAG_SEPARATE)
         zd = empty_dev(dims, dtype)
         plain.exec_fwd(xd, zd)
         assert np.array_equal(to_host(yd), to_host(zd))
