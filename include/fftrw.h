@@ -86,7 +86,9 @@ enum {
                                         segments (default: one fused permutation) */
     FFTRW_FLAG_COUNT_MOVED = 4u,     /* count, on the device, the points whose
                                         owner changes in every transpose          */
-    FFTRW_FLAG_OWN_MATCHED = 8u,     /* ownership reading R2 (see fft_comm_volume)*/
+    FFTRW_FLAG_OWN_MATCHED = 8u,     /* ownership reading R2 (see fft_comm_volume):
+                                        device counts, and with STAGED the
+                                        exchange itself, follow the matching     */
     FFTRW_FLAG_FUSED_FFT = 16u,      /* fuse each FFT step with the transpose that
                                         follows it (one HBM pass per step).  The
                                         default: a plan fuses whenever every step
@@ -300,7 +302,8 @@ int fft_plan_stats(fft_plan_t plan, int64_t *per_step, int64_t *moved);
  * fft_plan_messages -- for a plan built with FFTRW_FLAG_STAGED, the number of
  * messages of each transpose's all-to-all: the (p, q) pairs with p != q that
  * exchange at least one point (Fig. 4's transposes, as a distributed run
- * would send them).  per_step[M] receives transposes 1..M-1 then the return
+ * would send them); with FFTRW_FLAG_OWN_MATCHED, the pairs that share points
+ * other than each range and its matched range.  per_step[M] receives transposes 1..M-1 then the return
  * transpose.  FFTRW_E_UNSUPPORTED for plans without staged tables.
  */
 int fft_plan_messages(fft_plan_t plan, int64_t *per_step);

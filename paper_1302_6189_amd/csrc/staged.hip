@@ -69,10 +69,11 @@ struct RankBox {
 
 struct RecvInfo {              // destination q: its range in B
     int64_t start;             // first point of the range = start of q's receive region
-    int64_t kept;              // points q owns in both A and B (never exchanged)
-    int64_t selfbase;          // D(q, q)
+    int64_t kept;              // points of q's range that stay with their process (never exchanged)
+    int64_t selfbase;          // D(ksrc, q)
     int first_b[kMaxDims];     // q's first point, coordinates in B's order
-    int pad;
+    int ksrc;                  // the source range whose points q keeps: q under the literal
+                               // reading, the range matched to q under the matched one
     RankBox box[kRangeBoxes];  // in A's order
 };
 
@@ -188,7 +189,7 @@ __device__ __forceinline__ int own_lookup(const int *keys, const int *num, int k
 }
 
 struct TileLds {
-    size_t tile, gbase, gc, r0, wv, rb, sb, kp, pt, own_a, own_b, hash, misc, total;
+    size_t tile, gbase, gc, r0, wv, rb, sb, kp, ks, pt, own_a, own_b, hash, misc, total;
 };
 
 __host__ __device__ inline TileLds tile_lds(int lu, int lv, int lg, size_t esz, bool pack)
@@ -210,6 +211,7 @@ __host__ __device__ inline TileLds tile_lds(int lu, int lv, int lg, size_t esz, 
     L.rb = pack ? 0 : take(G * TU * 4);
     L.sb = pack ? 0 : take(G * TU * 4);
     L.kp = pack ? 0 : take(G * TU * 4);
+    L.ks = pack ? 0 : take(G * TU * 4);
     L.pt = pack ? take(kPairTab * 4) : 0;
     L.own_a = take(G * TV * 4);
     L.own_b = take(G * TU * 4);
@@ -289,6 +291,7 @@ __global__ void __launch_bounds__(kThreads)
     int *rb = reinterpret_cast<int *>(smem + L.rb);
     int *sb = reinterpret_cast<int *>(smem + L.sb);
     int *kp = reinterpret_cast<int *>(smem + L.kp);
+    int *ks = reinterpret_cast<int *>(smem + L.ks);
     int *pt = reinterpret_cast<int *>(smem + L.pt);
     int *own_a = reinterpret_cast<int *>(smem + L.own_a);
     int *own_b = reinterpret_cast<int *>(smem + L.own_b);
@@ -361,6 +364,7 @@ __global__ void __launch_bounds__(kThreads)
             rb[k] = (int)R.start;
             sb[k] = (int)R.selfbase;
             kp[k] = (int)R.kept;
+            ks[k] = R.ksrc;
             continue;
         }
         const int *bc = gc + 3 * g;
@@ -441,11 +445,12 @@ __global__ void __launch_bounds__(kThreads)
                 const int rk = r0[k] + iv * wv[k];
                 const C *from = src;
                 int off;
-                if (p == q) {
+                const int keep_src = ks[k];
+                if (p == keep_src) {
                     from = self_src;
                     off = sb[k] + rk;
                 } else {
-                    off = rb[k] + rk - (p > q ? kp[k] : 0);
+                    off = rb[k] + rk - (p > keep_src ? kp[k] : 0);
                 }
                 val[j] = (uint32_t)off < (uint32_t)a.T ? xld(from + off) : mk<C>(0, 0);
             }
@@ -767,8 +772,6 @@ StagedTileCfg make_tile(const fft_plan_impl *pl, int t, int seg_axis, bool pack)
 
 int staged_build(fft_plan_impl *pl, int t)
 {
-    if (pl->ownership != FFTRW_OWN_LITERAL)
-        return fail(FFTRW_E_UNSUPPORTED, "staged transposes use the literal ownership reading");
     const Layout &a = pl->lay[t];
     const Layout &b = pl->lay[t + 1];
     const int M = pl->M;
@@ -786,12 +789,22 @@ int staged_build(fft_plan_impl *pl, int t)
             pl->dev_bytes += (size_t)pl->T * pl->esz;
         }
     }
-    // every (p, q) pair that shares points, by p then q
+    // every (p, q) pair that shares points, by p then q.  Range p of A is held
+    // by the process that keeps range mu[p] of B (mu = identity under the
+    // literal reading, the plan's maximum matching under the matched one), so
+    // the pair (p, mu[p]) stays put and every other pair is a message.
     const std::vector<PairCount> pc = pair_counts(a, b);
+    const std::vector<i64> &mu = pl->mu[t];
+    if ((i64)mu.size() != P) return fail(FFTRW_E_DEVICE, "internal: relabelling table size");
     std::vector<RecvInfo> ri(P);
+    for (i64 p = 0; p < P; ++p) {
+        ri[mu[p]].ksrc = (int)p;
+        ri[mu[p]].kept = 0;
+        ri[mu[p]].selfbase = 0;
+    }
     std::vector<SendInfo> si(P);
     std::vector<i64> before_q(P, 0);   // points of Q_q in the ranges of sources < p
-    std::vector<i64> recv_fill(P, 0);  // received points of q so far (sources != q)
+    std::vector<i64> recv_fill(P, 0);  // received points of q so far (sources other than ksrc)
     std::vector<SegCopy> segs;
     i64 moved = 0;
     {
@@ -801,7 +814,7 @@ int staged_build(fft_plan_impl *pl, int t)
             i64 segoff = 0;
             for (; i < pc.size() && pc[i].p == p; ++i) {
                 const i64 q = pc[i].q, n = pc[i].n;
-                if (p == q) {
+                if (q == mu[p]) {
                     ri[q].kept = n;
                     ri[q].selfbase = xs + segoff - before_q[q];
                 } else {
@@ -824,7 +837,6 @@ int staged_build(fft_plan_impl *pl, int t)
         i64 st[kMaxDims];
         range_of(b, q, nullptr, nullptr, st, nullptr);
         for (int i = 0; i < kMaxDims; ++i) r.first_b[i] = i < M ? (int)st[i] : 0;
-        r.pad = 0;
         const std::vector<Box> boxes = range_boxes(b, q);
         if ((int)boxes.size() > kRangeBoxes) return fail(FFTRW_E_DEVICE, "internal: too many range boxes");
         nbq = std::max(nbq, (int)boxes.size());

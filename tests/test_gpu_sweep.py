@@ -15,7 +15,7 @@ from tests.gpu_util import empty_dev, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 SIZES = [1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16, 18, 20, 24, 25, 27, 30, 32, 36, 40, 45, 48, 64]
-MODES = {"fused": fftrw.FLAG_FUSED_FFT, "separate": 0, "staged": fftrw.FLAG_STAGED}
+MODES = {"fused": fftrw.FLAG_FUSED_FFT, "separate": fftrw.FLAG_SEPARATE, "staged": fftrw.FLAG_STAGED}
 TOL = {np.complex64: 1e-5, np.complex128: 1e-12}
 
 
@@ -70,14 +70,17 @@ def test_random_plans(gpu_lib, dims, P, idx, mode, dtype):
 
 @pytest.mark.parametrize("dims,P,idx,mode,dtype", _cases(30, seed=13026189 + 8))
 def test_random_plans_matched(gpu_lib, dims, P, idx, mode, dtype):
-    if mode == "staged":
-        pytest.skip("the staged path keeps the literal reading")
     M = len(dims)
     order = fftrw.fft_order_at(M, idx)
     try:
         plan = fftrw.Plan(dims, P, order, flags=MODES[mode] | fftrw.FLAG_COUNT_MOVED | fftrw.FLAG_OWN_MATCHED)
     except fftrw.FftrwError as e:
-        assert e.code == fftrw.E_UNSUPPORTED  # an overlap component past the exact assignment's limit
+        if e.code == fftrw.E_ROWSPLIT:
+            # staged transposes need whole rows, exactly as under the literal reading
+            assert mode == "staged"
+            assert any(decomp.level([dims[a] for a in p], P) >= M for p in order)
+        else:
+            assert e.code == fftrw.E_UNSUPPORTED  # an overlap component past the exact assignment's limit
         return
     x = inputs.uniform(dims, 3, np.complex64)
     xd = to_dev(x)
