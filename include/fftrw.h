@@ -337,6 +337,30 @@ int fft_plan_describe(fft_plan_t plan, int8_t *order, char *text, size_t cap);
 
 int fft_destroy(fft_plan_t plan);
 
+/*
+ * fft_exec_noalloc -- for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): plan and run the whole pipeline of fft_exec_fwd (direction -1)
+ * or fft_exec_inv (+1) in one call, allocating nothing on the device.  The
+ * arguments mean what they mean for fft_plan and fft_exec_*; in and out are
+ * caller-owned device buffers of T elements (in == out allowed; otherwise in
+ * is not modified).  The workspace and twiddle tables live in one fixed
+ * device array of the library (64 MiB of workspace plus 1 MiB for tables;
+ * each GPU the library runs on holds its own copy until the process ends), so
+ * T * element size must be at most 64 MiB (8,388,608 complex64 points,
+ * 4,194,304 complex128): larger arrays return FFTRW_E_SIZE.  flags: only
+ * LEAVE_PERMUTED, FUSED_FFT, SEPARATE (FFTRW_E_UNSUPPORTED otherwise: staged
+ * tables, device counters and relabelling tables would need memory of their
+ * own).  Results equal fft_plan + fft_exec_* with the same arguments bit for
+ * bit.  Asynchronous on `stream`.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams or threads) race; calls
+ * on one stream are ordered.  The host side allocates only host memory.
+ * Errors: as fft_plan, plus FFTRW_E_ARG for a direction other than -1 / +1.
+ */
+int fft_exec_noalloc(int M, const int64_t *dims, int64_t P, const int8_t *order,
+                     int dtype, int precision, unsigned flags, int direction,
+                     const void *in, void *out, void *stream);
+
 /* ---- batched form: many uneven transforms in one persistent launch ------- */
 
 /* One item of a batch: an M-D complex64 transform of sizes dims[0..M) over P

@@ -192,7 +192,7 @@ __global__ void batch_reset_kernel(unsigned long long *p, int64_t n)
 namespace fftrw {
 
 int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8_t *order, int dtype,
-                int precision, unsigned flags, bool generic_rows, const TuneTable *tune);
+                int precision, unsigned flags, bool generic_rows, const TuneTable *tune, DevArena *arena);
 void plan_free(fft_plan_t plan);
 
 struct fft_batch_impl {
@@ -306,7 +306,7 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
         const fft_item_desc &it = items[i];
         fft_plan_t p = nullptr;
         int rc = plan_create(&p, it.M, it.dims, it.P, it.has_order ? it.order : nullptr, FFTRW_C64,
-                             FFTRW_PREC_NATIVE, pflags, true, tuned ? &tune : nullptr);
+                             FFTRW_PREC_NATIVE, pflags, true, tuned ? &tune : nullptr, nullptr);
         if (rc) {
             std::string m = "item " + std::to_string(i) + ": " + g_last_error;
             batch_free(b);

@@ -257,6 +257,17 @@ void free_plan(fft_plan_impl *pl)
 int dev_alloc(fft_plan_impl *pl, void **p, size_t bytes)
 {
     if (bytes == 0) bytes = 16;
+    if (pl->arena) {
+        DevArena &a = *pl->arena;
+        const size_t off = (a.used + 255) & ~(size_t)255;
+        if (off > a.cap || bytes > a.cap - off)
+            return fail(FFTRW_E_SIZE, "the fixed device region holds " + std::to_string(a.cap) + " bytes, " +
+                                          std::to_string(off + bytes) + " needed");
+        *p = a.base + off;
+        a.used = off + bytes;
+        pl->dev_bytes += bytes;
+        return FFTRW_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -363,7 +374,7 @@ int run_pipeline(fft_plan_impl *pl, const void *in, void *out, hipStream_t s, in
 // Build a plan; generic_rows forces the runtime-radix row kernel for every
 // step (the persistent batched kernel runs only that one).
 int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8_t *order, int dtype,
-                int precision, unsigned flags, bool generic_rows, const TuneTable *tune)
+                int precision, unsigned flags, bool generic_rows, const TuneTable *tune, DevArena *arena)
 {
     g_last_error.clear();
     if (!plan) return fail(FFTRW_E_ARG, "plan must not be null");
@@ -391,6 +402,7 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
     pl->dtype = dtype;
     pl->precision = precision;
     pl->flags = flags;
+    pl->arena = arena;
     pl->ownership = (flags & FFTRW_FLAG_OWN_MATCHED) ? FFTRW_OWN_MATCHED : FFTRW_OWN_LITERAL;
     pl->esz = dtype == FFTRW_C64 ? 8 : 16;
     pl->T = 1;
@@ -455,8 +467,9 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
                 free_plan(pl);
                 return rc;
             }
-            hipError_t e = (pl->fft[t].pow2 && !pl->fft[t].mfma) ? pow2_make_twiddles(N, pl->esz == 16, tw, nullptr)
-                                                                 : launch_twiddles(tw, N, pl->esz == 16, nullptr);
+            hipStream_t ts = arena ? arena->stream : nullptr;
+            hipError_t e = (pl->fft[t].pow2 && !pl->fft[t].mfma) ? pow2_make_twiddles(N, pl->esz == 16, tw, ts)
+                                                                 : launch_twiddles(tw, N, pl->esz == 16, ts);
             if (e != hipSuccess) {
                 free_plan(pl);
                 return hip_fail(e, "twiddle generation");
@@ -528,7 +541,9 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
         }
         pl->fused = ok;
     }
-    if (hipDeviceSynchronize() != hipSuccess) {
+    // (an arena plan only enqueues: its caller's stream orders the twiddle
+    // kernels before the transform)
+    if (!arena && hipDeviceSynchronize() != hipSuccess) {
         free_plan(pl);
         return fail(FFTRW_E_DEVICE, "device error during plan creation");
     }
@@ -550,6 +565,11 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
 
 void plan_free(fft_plan_t plan) { free_plan(plan); }
 
+int plan_run(fft_plan_impl *pl, const void *in, void *out, hipStream_t s, int dir)
+{
+    return run_pipeline(pl, in, out, s, dir);
+}
+
 }  // namespace fftrw
 
 using namespace fftrw;
@@ -559,7 +579,7 @@ extern "C" {
 int fft_plan(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const int8_t *order, int dtype,
              int precision, unsigned flags)
 {
-    return fftrw::plan_create(plan, M, dims, P, order, dtype, precision, flags, false, nullptr);
+    return fftrw::plan_create(plan, M, dims, P, order, dtype, precision, flags, false, nullptr, nullptr);
 }
 
 int fft_exec_fwd(fft_plan_t plan, const void *in, void *out, void *stream)

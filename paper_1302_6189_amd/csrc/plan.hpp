@@ -35,6 +35,14 @@ struct StagedStep {
     StagedTileCfg pack, unpack;   // tilings of the two kernels
 };
 
+// Device memory handed to a plan in place of hipMalloc: bump allocation from
+// a fixed region (nothing is freed), twiddle tables generated on `stream`.
+struct DevArena {
+    unsigned char *base = nullptr;
+    size_t cap = 0, used = 0;
+    hipStream_t stream = nullptr;
+};
+
 struct fft_plan_impl {
     int M = 0;
     i64 dims[kMaxDims] = {};
@@ -60,6 +68,7 @@ struct fft_plan_impl {
     void *send = nullptr, *recv = nullptr;
     unsigned long long *counters = nullptr;
     std::vector<void *> allocs;
+    DevArena *arena = nullptr;          // set: device memory comes from the arena, never hipMalloc
     std::map<int, void *> twiddles;
     size_t dev_bytes = 0;
     bool executed = false;

@@ -67,6 +67,8 @@ _SIGNATURES = {
     "fft_compare_models": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     "fft_plan": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _i64p, ctypes.c_int64, _i8p,
                                 ctypes.c_int, ctypes.c_int, ctypes.c_uint]),
+    "fft_exec_noalloc": (ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, _i8p, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_uint, ctypes.c_int, _vp, _vp, _vp]),
     "fft_exec_fwd": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "fft_exec_inv": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "fft_exec_fft_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
@@ -269,6 +271,17 @@ def _stream(stream):
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
+
+
+def fft_exec_noalloc(dims, P, order, direction, x, y, dtype: int = C64, precision: int = PREC_NATIVE,
+                     flags: int = 0, stream=None):
+    """fft_exec_noalloc: plan and run one transform without device allocation
+    (workspace in the library's fixed device array)."""
+    dims = tuple(int(d) for d in dims)
+    M = len(dims)
+    ordp = _order(order_from(order, M)) if order is not None else None
+    _check(lib().fft_exec_noalloc(M, _dims(dims), int(P), ordp, int(dtype), int(precision), ctypes.c_uint(int(flags)),
+                                  int(direction), _ptr(x), _ptr(y), _stream(stream)))
 
 
 class Plan:
