@@ -58,9 +58,10 @@ enum {
     FFTRW_E_ORDER = -3,       /* malformed permutation or transpose order      */
     FFTRW_E_ROWSPLIT = -4,    /* N_p > T (no level of Eq. (13) applies); or a
                                  step at level M (N_p > T / N_last: rows along
-                                 its FFT axis split over processes) where whole
-                                 rows are needed (staged transposes), or as a
-                                 flag from fft_comm_volume (see there)          */
+                                 its FFT axis split over processes) that a
+                                 staged plan cannot run as a binary exchange
+                                 (see fft_plan_rowsplit_stats), or as a flag
+                                 from fft_comm_volume (see there)               */
     FFTRW_E_NOMEM = -5,       /* host or device allocation failed             */
     FFTRW_E_DEVICE = -6,      /* a HIP call failed; see fft_last_error()       */
     FFTRW_E_UNSUPPORTED = -7  /* combination not implemented                   */
@@ -241,7 +242,9 @@ int fft_compare_models(double N, double P, double *out);
  * 1 <= P <= T.  Steps at level M of Eq. (13) (P > T / N_last, rows split
  * along the FFT axis) run: the processes sharing a row share device memory,
  * so the row is transformed whole, and the transposes are counted exactly as
- * at other levels; staged transposes refuse them (FFTRW_E_ROWSPLIT).
+ * at other levels.  Staged plans run such a step's split rows as a binary
+ * exchange (see fft_plan_rowsplit_stats), and its transposes as the counted
+ * fused permutation.
  * Fusion: unless flags hold FFTRW_FLAG_SEPARATE or FFTRW_FLAG_STAGED, each
  * FFT step runs fused with the transpose that follows it when every step
  * qualifies (power-of-two rows of 16..512 points for C64, 16..256 for C128,
@@ -303,10 +306,29 @@ int fft_plan_stats(fft_plan_t plan, int64_t *per_step, int64_t *moved);
  * messages of each transpose's all-to-all: the (p, q) pairs with p != q that
  * exchange at least one point (Fig. 4's transposes, as a distributed run
  * would send them); with FFTRW_FLAG_OWN_MATCHED, the pairs that share points
- * other than each range and its matched range.  per_step[M] receives transposes 1..M-1 then the return
+ * other than each range and its matched range.  -1 for a transpose that
+ * touches a decomposition at level M: staged plans run it as the fused
+ * permutation, its owner changes counted (see fft_plan_stats).  per_step[M] receives transposes 1..M-1 then the return
  * transpose.  FFTRW_E_UNSUPPORTED for plans without staged tables.
  */
 int fft_plan_messages(fft_plan_t plan, int64_t *per_step);
+
+/*
+ * fft_plan_rowsplit_stats -- for a plan built with FFTRW_FLAG_STAGED, the
+ * exchange of the FFT steps whose rows are split over processes (level M of
+ * Eq. (13), N_p > T / N_last).  A staged plan runs such a step as a binary
+ * exchange among the processes that share each row (the reading of
+ * fft_rowsplit_volume): it needs every range to hold b = T / N_p points and
+ * each row to be c = N / b ranges with c a power of two (otherwise fft_plan
+ * returns FFTRW_E_ROWSPLIT), and sends every point once in each of the
+ * log2 c stages.
+ *   per_step[M] (nullable): fft_rowsplit_volume's count for each FFT step
+ *       (0 below level M), or -1 for a plan that is not staged.
+ *   moved[M] (nullable): points copied between processes by the last exec's
+ *       split-row exchanges, counted on the device; -1 where not executed.
+ * Synchronises the device.
+ */
+int fft_plan_rowsplit_stats(fft_plan_t plan, int64_t *per_step, int64_t *moved);
 
 /*
  * fft_plan_set_timing -- when enable != 0, every later exec records a HIP

@@ -17,7 +17,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HIP_SOURCES = ["fft_rows.hip", "fft_pow2.hip", "fft_mfma.hip", "transpose.hip", "staged.hip", "exec.hip", "batch.hip",
-               "autotune.hip", "noalloc.hip"]
+               "autotune.hip", "noalloc.hip", "rowsplit.hip"]
 CXX_SOURCES = ["decomp.cpp", "capi_host.cpp"]
 
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

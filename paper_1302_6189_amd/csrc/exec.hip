@@ -43,6 +43,12 @@ hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in,
 hipError_t launch_xpose(const XposeDesc &d, size_t esz, const void *in, void *out, hipStream_t s);
 size_t xpose_lds_bytes(const XposeDesc &d, size_t esz);
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
+hipError_t launch_bx_exchange(bool fp64, const void *data, void *recv, int64_t T, int N, int b, int hb,
+                              unsigned long long *counter, hipStream_t s);
+hipError_t launch_bx_butterfly(bool fp64, int dir, void *data, const void *recv, int64_t T, int N, int h,
+                               const void *tw, hipStream_t s);
+hipError_t launch_bx_unscramble(bool fp64, const void *in, void *out, int64_t T, int N, int b, int sbits,
+                                double scale, hipStream_t s);
 int staged_build(fft_plan_impl *pl, int t);
 int staged_run(fft_plan_impl *pl, int t, const void *in, void *out, hipStream_t s);
 int staged_part(fft_plan_impl *pl, int t, int part, const void *in, void *out, hipStream_t s);
@@ -113,10 +119,8 @@ i64 pow2ceil(i64 x)
     return p;
 }
 
-int make_fft_desc(fft_plan_impl *pl, int t, FftDesc *d, bool generic_rows, const TuneTable *tune)
+int make_len_desc(fft_plan_impl *pl, i64 N, FftDesc *d, bool generic_rows, const TuneTable *tune)
 {
-    const int ax = pl->order[t * pl->M + pl->M - 1];
-    const i64 N = pl->dims[ax];
     if (!smooth235(N) || N > 4096)
         return fail(FFTRW_E_SIZE, "row length " + std::to_string(N) + " must be 2^a 3^b 5^c and <= 4096");
     std::memset(d, 0, sizeof(*d));
@@ -163,6 +167,27 @@ int make_fft_desc(fft_plan_impl *pl, int t, FftDesc *d, bool generic_rows, const
     d->rows_per_wg = (int)rw;
     d->lanes_per_row = (int)(256 / rw);
     d->nrows = pl->T / N;
+    return FFTRW_OK;
+}
+
+int make_fft_desc(fft_plan_impl *pl, int t, FftDesc *d, bool generic_rows, const TuneTable *tune)
+{
+    const int ax = pl->order[t * pl->M + pl->M - 1];
+    return make_len_desc(pl, pl->dims[ax], d, generic_rows, tune);
+}
+
+int dev_alloc(fft_plan_impl *pl, void **p, size_t bytes);
+
+// The twiddle table a descriptor's kernel reads: the per-pass table of the
+// compile-time power-of-two kernel, else w_N^e for e < N, generated on the
+// device in FP64 and rounded.
+int make_desc_twiddles(fft_plan_impl *pl, const FftDesc &d, void **tw)
+{
+    if (int rc = dev_alloc(pl, tw, (size_t)std::max(1, d.tw_count) * pl->esz)) return rc;
+    hipStream_t ts = pl->arena ? pl->arena->stream : nullptr;
+    hipError_t e = (d.pow2 && !d.mfma) ? pow2_make_twiddles(d.N, pl->esz == 16, *tw, ts)
+                                       : launch_twiddles(*tw, d.N, pl->esz == 16, ts);
+    if (e != hipSuccess) return hip_fail(e, "twiddle generation");
     return FFTRW_OK;
 }
 
@@ -278,9 +303,9 @@ int dev_alloc(fft_plan_impl *pl, void **p, size_t bytes)
     return FFTRW_OK;
 }
 
-int run_fft_step(fft_plan_impl *pl, int t, int dir, const void *in, void *out, double scale, hipStream_t s)
+int run_fft_desc(fft_plan_impl *pl, const FftDesc &d, int dir, const void *in, void *out, double scale,
+                 hipStream_t s)
 {
-    const FftDesc &d = pl->fft[t];
     if (d.mfma) {
         HIP_TRY(launch_fft256_mfma(d.mfma, dir, d.tw, d.nrows, in, out, scale, s), "mfma fft pass launch");
         return FFTRW_OK;
@@ -293,9 +318,39 @@ int run_fft_step(fft_plan_impl *pl, int t, int dir, const void *in, void *out, d
     return FFTRW_OK;
 }
 
+// Step t at level M in a staged plan: the split rows' binary exchange (see
+// rowsplit.hip), then b-point DFTs of the blocks and the permutation to
+// natural order within each row.  Works in place on `out` (copied from `in`
+// first when they differ); the staging receive array carries the messages.
+int run_split_step(fft_plan_impl *pl, int t, int dir, const void *in, void *out, double scale, hipStream_t s)
+{
+    const SplitStep &sp = pl->split[t];
+    const bool fp64 = pl->esz == 16;
+    const int N = pl->fft[t].N;
+    if (in != out)
+        HIP_TRY(hipMemcpyAsync(out, in, (size_t)pl->T * pl->esz, hipMemcpyDeviceToDevice, s), "split-row copy");
+    unsigned long long *ctr = pl->counters + (size_t)(pl->M + t) * kCountBlock;
+    for (int st = 0; st < sp.s; ++st) {
+        const int h = N >> (st + 1);
+        HIP_TRY(launch_bx_exchange(fp64, out, pl->recv, pl->T, N, sp.b, h / sp.b, ctr, s), "split-row exchange");
+        HIP_TRY(launch_bx_butterfly(fp64, dir, out, pl->recv, pl->T, N, h, sp.tw, s), "split-row butterflies");
+    }
+    if (sp.b > 1)
+        if (int rc = run_fft_desc(pl, sp.local, dir, out, out, 1.0, s)) return rc;
+    HIP_TRY(launch_bx_unscramble(fp64, out, pl->recv, pl->T, N, sp.b, sp.s, scale, s), "split-row order");
+    HIP_TRY(hipMemcpyAsync(out, pl->recv, (size_t)pl->T * pl->esz, hipMemcpyDeviceToDevice, s), "split-row copy");
+    return FFTRW_OK;
+}
+
+int run_fft_step(fft_plan_impl *pl, int t, int dir, const void *in, void *out, double scale, hipStream_t s)
+{
+    if (!pl->split.empty() && pl->split[t].c > 0) return run_split_step(pl, t, dir, in, out, scale, s);
+    return run_fft_desc(pl, pl->fft[t], dir, in, out, scale, s);
+}
+
 int run_transpose(fft_plan_impl *pl, int t, const void *in, void *out, hipStream_t s)
 {
-    if (pl->flags & FFTRW_FLAG_STAGED) return staged_run(pl, t, in, out, s);
+    if ((pl->flags & FFTRW_FLAG_STAGED) && pl->xp_staged[t]) return staged_run(pl, t, in, out, s);
     HIP_TRY(launch_xpose(pl->xp[t], pl->esz, in, out, s), "transpose launch");
     return FFTRW_OK;
 }
@@ -305,7 +360,7 @@ int run_pipeline(fft_plan_impl *pl, const void *in, void *out, hipStream_t s, in
     const int M = pl->M;
     const bool leave = (pl->flags & FFTRW_FLAG_LEAVE_PERMUTED) != 0;
     const int nx = leave ? M - 1 : M;
-    if (pl->counters) HIP_TRY(launch_zero_u64(pl->counters, M * kCountBlock, s), "counter reset");
+    if (pl->counters) HIP_TRY(launch_zero_u64(pl->counters, pl->n_counters, s), "counter reset");
     int nev = 0;
     auto mark = [&]() -> int {
         if (!pl->timing) return FFTRW_OK;
@@ -350,7 +405,7 @@ int run_pipeline(fft_plan_impl *pl, const void *in, void *out, hipStream_t s, in
         int rc = run_fft_step(pl, t, dir, t == 0 ? in : cur, cur, scale, s);
         if (rc || (rc = mark())) return rc;
         if (t < nx) {
-            if (pl->timing && (pl->flags & FFTRW_FLAG_STAGED)) {
+            if (pl->timing && (pl->flags & FFTRW_FLAG_STAGED) && pl->xp_staged[t]) {
                 // pack, exchange and unpack as stages of their own
                 for (int part = 0; part < 3 && !rc; ++part) {
                     rc = staged_part(pl, t, part, cur, other, s);
@@ -478,10 +533,69 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
         }
         pl->fft[t].tw = pl->twiddles[N];
     }
-    // workspace and counters
+    // staged plans at level M: each split step must be c = 2^s whole ranges of
+    // b = T / N_p points per row, run as a binary exchange (rowsplit.hip)
+    bool any_split = false;
+    if (flags & FFTRW_FLAG_STAGED) {
+        pl->split.assign(M, SplitStep{});
+        pl->split_analytic.assign(M, 0);
+        int64_t tot = 0;
+        if ((rc = fft_rowsplit_volume(M, dims, P, pl->order, pl->split_analytic.data(), &tot))) {
+            free_plan(pl);
+            return rc;
+        }
+        for (int t = 0; t < M; ++t) {
+            if (!pl->lay[t].row_split()) continue;
+            const i64 N = pl->fft[t].N;
+            const i64 b = pl->T / P;
+            const i64 c = b > 0 && pl->T % P == 0 && N % b == 0 ? N / b : 0;
+            if (c < 2 || (c & (c - 1)) != 0) {
+                free_plan(pl);
+                return fail(FFTRW_E_ROWSPLIT,
+                            "staged plans run a step at level M (rows split over processes) as a binary exchange "
+                            "only when every range holds T / N_p points and each row is a power-of-two number of "
+                            "ranges; here T = " + std::to_string(pl->T) + ", N_p = " + std::to_string(P) +
+                                ", row length " + std::to_string(N));
+            }
+            SplitStep &sp = pl->split[t];
+            sp.b = (int)b;
+            sp.c = (int)c;
+            while ((1 << sp.s) < sp.c) ++sp.s;
+            FftDesc full = {};
+            full.N = (int)N;
+            full.tw_count = (int)N;  // w_N^e, e < N
+            if ((rc = make_desc_twiddles(pl, full, &sp.tw))) {
+                free_plan(pl);
+                return rc;
+            }
+            if (b > 1) {
+                if ((rc = make_len_desc(pl, b, &sp.local, false, tune)) ||
+                    (rc = make_desc_twiddles(pl, sp.local, const_cast<void **>(&sp.local.tw)))) {
+                    free_plan(pl);
+                    return rc;
+                }
+            }
+            any_split = true;
+        }
+    }
+    // workspace and counters (staged plans also count each split step's exchange)
     rc = dev_alloc(pl, &pl->work, (size_t)pl->T * pl->esz);
-    if (!rc && (flags & (FFTRW_FLAG_COUNT_MOVED | FFTRW_FLAG_STAGED)))
-        rc = dev_alloc(pl, (void **)&pl->counters, sizeof(unsigned long long) * (size_t)M * kCountBlock);
+    if (!rc && (flags & (FFTRW_FLAG_COUNT_MOVED | FFTRW_FLAG_STAGED))) {
+        pl->n_counters = ((flags & FFTRW_FLAG_STAGED) ? 2 : 1) * M * kCountBlock;
+        rc = dev_alloc(pl, (void **)&pl->counters, sizeof(unsigned long long) * (size_t)pl->n_counters);
+    }
+    if (!rc && any_split && !pl->send) {
+        // the staging arrays (freed with the staged tables); the split steps'
+        // messages go through the receive array
+        for (void **buf : {&pl->send, &pl->recv}) {
+            if (hipMalloc(buf, (size_t)pl->T * pl->esz) != hipSuccess) {
+                (void)hipGetLastError();
+                rc = fail(FFTRW_E_NOMEM, "hipMalloc of staging buffers failed");
+                break;
+            }
+            pl->dev_bytes += (size_t)pl->T * pl->esz;
+        }
+    }
     if (rc) {
         free_plan(pl);
         return rc;
@@ -506,15 +620,21 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
     pl->xp.resize(M);
     pl->staged.resize(M);
     for (int t = 0; t < M; ++t) {
-        unsigned long long *ctr =
-            (flags & FFTRW_FLAG_COUNT_MOVED) ? pl->counters + (size_t)t * kCountBlock : nullptr;
+        // staged plans: transposes between whole-row layouts run pack ->
+        // exchange -> unpack; one that touches a level-M layout (rows split)
+        // runs the fused permutation with its owner changes counted
+        const bool staged = (flags & FFTRW_FLAG_STAGED) && !pl->lay[t].row_split() && !pl->lay[t + 1].row_split();
+        pl->xp_staged[t] = staged;
+        unsigned long long *ctr = (flags & (FFTRW_FLAG_COUNT_MOVED | FFTRW_FLAG_STAGED))
+                                      ? pl->counters + (size_t)t * kCountBlock
+                                      : nullptr;
         rc = make_xpose_desc(pl, pl->lay[t], pl->lay[t + 1], &pl->mu[t], ctr, &pl->xp[t], tune);
         if (rc) {
             free_plan(pl);
             return rc;
         }
         pl->xp[t].mu = mu_dev[t];
-        if (flags & FFTRW_FLAG_STAGED) {
+        if (staged) {
             rc = staged_build(pl, t);
             if (rc) {
                 free_plan(pl);
@@ -656,7 +776,34 @@ int fft_plan_messages(fft_plan_t plan, int64_t *per_step)
     g_last_error.clear();
     if (!plan || !per_step) return fail(FFTRW_E_ARG, "null plan or output");
     if (!(plan->flags & FFTRW_FLAG_STAGED)) return fail(FFTRW_E_UNSUPPORTED, "the plan has no staged tables");
-    for (int t = 0; t < plan->M; ++t) per_step[t] = plan->staged[t].nseg;
+    for (int t = 0; t < plan->M; ++t) per_step[t] = plan->xp_staged[t] ? plan->staged[t].nseg : -1;
+    return FFTRW_OK;
+}
+
+int fft_plan_rowsplit_stats(fft_plan_t plan, int64_t *per_step, int64_t *moved)
+{
+    g_last_error.clear();
+    if (!plan) return fail(FFTRW_E_ARG, "null plan");
+    const int M = plan->M;
+    const bool staged = (plan->flags & FFTRW_FLAG_STAGED) != 0;
+    if (per_step)
+        for (int t = 0; t < M; ++t) per_step[t] = staged ? plan->split_analytic[t] : -1;
+    if (moved) {
+        for (int t = 0; t < M; ++t) moved[t] = -1;
+        if (staged && plan->executed) {
+            std::vector<unsigned long long> h((size_t)M * kCountBlock);
+            if (hipDeviceSynchronize() != hipSuccess)
+                return fail(FFTRW_E_DEVICE, "device error before reading counters");
+            if (hipMemcpy(h.data(), plan->counters + (size_t)M * kCountBlock, sizeof(unsigned long long) * h.size(),
+                          hipMemcpyDeviceToHost) != hipSuccess)
+                return fail(FFTRW_E_DEVICE, "reading counters failed");
+            for (int t = 0; t < M; ++t) {
+                unsigned long long sum = 0;
+                for (int k = 0; k < kCountSlots; ++k) sum += h[(size_t)t * kCountBlock + (size_t)k * kCountStride];
+                moved[t] = (int64_t)sum;
+            }
+        }
+    }
     return FFTRW_OK;
 }
 

@@ -43,6 +43,15 @@ struct DevArena {
     hipStream_t stream = nullptr;
 };
 
+// An FFT step at level M run as a binary exchange among the processes that
+// share each row (staged plans; see rowsplit.hip): every range holds b points,
+// a row is c = 2^s ranges.
+struct SplitStep {
+    int b = 0, c = 0, s = 0;      // c = 0: the step's rows are whole
+    void *tw = nullptr;           // w_N^e, e < N (the butterflies' twiddles)
+    FftDesc local = {};           // the b-point DFTs of the blocks (b > 1)
+};
+
 struct fft_plan_impl {
     int M = 0;
     i64 dims[kMaxDims] = {};
@@ -62,11 +71,15 @@ struct fft_plan_impl {
     std::vector<i64> analytic;          // M: steps then return transpose
     std::vector<std::vector<i64>> mu;   // per transpose relabelling (matched)
     std::vector<StagedStep> staged;     // per transpose (STAGED flag)
+    bool xp_staged[kMaxDims] = {};      // transpose t runs through staged tables
+    std::vector<SplitStep> split;       // per step (staged plans at level M)
+    std::vector<i64> split_analytic;    // per step: points the split rows' exchange moves
 
     // device memory
     void *work = nullptr;
     void *send = nullptr, *recv = nullptr;
-    unsigned long long *counters = nullptr;
+    unsigned long long *counters = nullptr;  // M blocks (transposes), + M (split-row exchanges) when staged
+    int n_counters = 0;                      // 64-bit words in counters
     std::vector<void *> allocs;
     DevArena *arena = nullptr;          // set: device memory comes from the arena, never hipMalloc
     std::map<int, void *> twiddles;

@@ -75,6 +75,7 @@ _SIGNATURES = {
     "fft_exec_transpose": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     "fft_plan_stats": (ctypes.c_int, [_vp, _i64p, _i64p]),
     "fft_plan_messages": (ctypes.c_int, [_vp, _i64p]),
+    "fft_plan_rowsplit_stats": (ctypes.c_int, [_vp, _i64p, _i64p]),
     "fft_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "fft_plan_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
     "fft_plan_timings": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int,
@@ -324,6 +325,13 @@ class Plan:
 
     def set_timing(self, enable=True):
         _check(lib().fft_plan_set_timing(self._h, 1 if enable else 0))
+
+    def rowsplit_stats(self):
+        """(per-step split-row exchange amounts, device-counted copies of the last exec)."""
+        a = (ctypes.c_int64 * self.M)()
+        m = (ctypes.c_int64 * self.M)()
+        _check(lib().fft_plan_rowsplit_stats(self._h, a, m))
+        return list(a), list(m)
 
     def messages(self):
         """Messages of each staged transpose: (p, q) pairs, p != q, that exchange points."""

@@ -145,3 +145,65 @@ def test_row_split_items_in_a_batch(gpu_lib, flags):
         steps, ret = decomp.order_volumes(dims, P, order)
         assert st["analytic"][i] == steps + [ret]
         assert st["moved"][i] == st["analytic"][i], i
+
+
+# Staged plans at level M: the split rows' FFT runs as a binary exchange among
+# the processes sharing each row (every range b = T / N_p points, c = N / b a
+# power of two per row); transposes touching a level-M decomposition run as
+# the counted fused permutation, the others through pack -> exchange -> unpack.
+STAGED_SPLIT = [((64, 64, 64), 8192, 0),       # b = 32, c = 2 on every step
+                ((64, 64, 64), 16384, 5),      # b = 16, c = 4
+                ((16, 16, 16), 4096, 3),       # b = 1, c = 16: every point its own process
+                ((12, 24, 48), 4608, 6),       # b = 3 (3-point block DFTs), c = 4, 8, 16
+                ((64, 64, 16), 2048, 1),       # only the steps along a 64-point axis split (b = 32)
+                ((8, 8, 8, 8), 1024, 700),     # 4-D, b = 4, c = 2
+                ((8, 8, 8, 8, 8), 8192, 4000000)]  # 5-D, b = 4, c = 2
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+@pytest.mark.parametrize("dims,P,oidx", STAGED_SPLIT)
+def test_staged_split_rows_binary_exchange(gpu_lib, dims, P, oidx, dtype):
+    M = len(dims)
+    order = fftrw.fft_order_at(M, oidx)
+    plan = fftrw.Plan(dims, P, order, dtype=DT[dtype], flags=fftrw.FLAG_STAGED)
+    x = inputs.uniform(dims, 71 + oidx, dtype)
+    xd = to_dev(x)
+    yd = empty_dev(dims, dtype)
+    plan.exec_fwd(xd, yd)
+    ref = dft.fftn_direct(x, orders.fft_axis_sequence(order))
+    err = dft.rel_l2(to_host(yd), ref)
+    split_want = decomp.order_split_volumes(dims, P, order)
+    split_analytic, split_moved = plan.rowsplit_stats()
+    print(dims, P, orders.order_to_str(order), np.dtype(dtype).name, "rel-L2", err, "split", split_moved,
+          flush=True)
+    assert err < TOL[dtype]
+    # the split rows' exchange: N log2 c points per split row, counted as copied
+    assert split_analytic == split_want
+    assert split_moved == split_want
+    assert sum(split_want) > 0
+    # the transposes: owner changes, counted on the device, equal the oracle's
+    analytic, moved = plan.stats()
+    steps, ret = decomp.order_volumes(dims, P, order)
+    assert analytic == steps + [ret] and moved == analytic
+    # messages: staged transposes only (whole rows on both sides)
+    msgs = plan.messages()
+    seq = list(order) + [tuple(range(M))]
+    for t in range(M):
+        split_t = any(decomp.level([dims[a] for a in p], P) >= M for p in (seq[t], seq[t + 1]))
+        assert (msgs[t] == -1) == split_t, t
+    zd = empty_dev(dims, dtype)
+    plan.exec_inv(yd, zd)
+    assert dft.rel_l2(to_host(zd), x) < TOL[dtype]
+    assert plan.rowsplit_stats()[1] == split_want  # the inverse exchanges as much
+
+
+def test_staged_split_rows_refusals(gpu_lib):
+    # ranges that are not T / N_p points each, or rows that are not a power of
+    # two of them, have no binary exchange: staged plans refuse
+    for dims, P in [((8, 8, 8), 65), ((12, 10, 9), 500), ((20, 18, 24), 2880)]:
+        with pytest.raises(fftrw.FftrwError) as e:
+            fftrw.Plan(dims, P, fftrw.fft_order_at(3, 0), flags=fftrw.FLAG_STAGED)
+        assert e.value.code == fftrw.E_ROWSPLIT, (dims, P)
+    # below level M nothing changes
+    p = fftrw.Plan((16, 16, 16), 16, fftrw.fft_order_at(3, 0), flags=fftrw.FLAG_STAGED)
+    assert p.rowsplit_stats()[0] == [0, 0, 0]
