@@ -406,9 +406,11 @@ typedef struct fft_batch_s *fft_batch_t;
  * is its FFT step t fused with the transpose that follows (a unit: a block of
  * rows consecutive in the next layout's last axis); with BATCH_NO_FUSE the
  * FFT steps (row blocks) and transposes (tiles) are stages of their own.
- * Work-groups claim units from a per-level atomic counter and meet at a grid
- * barrier between levels; a wait past its time limit sets the error flag
- * reported by fft_batch_stats.  precision must be FFTRW_PREC_NATIVE; flags:
+ * Work-groups claim units from a per-level atomic counter; between levels
+ * each waits until every unit of the level is done (a count of completed
+ * units, so the wait ends even when other kernels keep part of the grid from
+ * being resident).  A wait past its time limit (2 s) adds one to a sticky
+ * time-out count that fft_batch_stats reports.  precision must be FFTRW_PREC_NATIVE; flags:
  * COUNT_MOVED, LEAVE_PERMUTED, BATCH_NO_GRAPH, BATCH_NO_FUSE.  tune_cache:
  * path of the autotuner's cache (fft_autotune) or NULL for the built-in plan.
  * Each item's row lengths follow fft_plan's rules; the batch owns one
@@ -429,10 +431,14 @@ int fft_batch_exec_inv(fft_batch_t batch, void *const *in, void *const *out,
 
 /*
  * fft_batch_stats -- moved (sum of M_i, nullable): device-counted owner
- * changes per transpose of every item (COUNT_MOVED), items in order;
- * analytic (same shape, nullable): the plan's amounts; units: number of work
- * units of one exec; error: nonzero if a unit's wait exceeded its limit in the
- * last exec (synchronises the device).
+ * changes per transpose of every item (COUNT_MOVED) in the last exec, items
+ * in order; analytic (same shape, nullable): the plan's amounts; units:
+ * number of work units of one exec; error (nullable): the number of level
+ * waits that exceeded their limit, summed over every exec of this batch so far
+ * (no launch resets it).  Synchronises the device.  When that count is not
+ * zero the call fills the outputs and returns FFTRW_E_DEVICE, and later execs
+ * of the batch return FFTRW_E_DEVICE: a timed-out exec's results are not
+ * reliable.
  */
 int fft_batch_stats(fft_batch_t batch, int64_t *moved, int64_t *analytic,
                     int64_t *units, int *error);

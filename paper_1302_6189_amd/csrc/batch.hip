@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -85,7 +86,7 @@ template <int DIR, bool TW_LDS>
 __global__ void __launch_bounds__(kThreads)
     batch_kernel(const BatchItemDev *__restrict__ items, const BatchTask *__restrict__ tasks,
                  const int *__restrict__ level_task0, const int64_t *__restrict__ level_units, int nlevels,
-                 BatchCounters *ctr, unsigned long long *timeouts)
+                 BatchCounters *ctr, unsigned long long *timeouts, unsigned long long wait_ticks)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t s_unit0[kLevelTasksLds];
@@ -168,7 +169,7 @@ __global__ void __launch_bounds__(kThreads)
             if (ndone) atomicAdd(&ctr->done[lv], ndone);
             const unsigned long long w0 = wall_clock64();
             while (__hip_atomic_load(&ctr->done[lv], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                if (wall_clock64() - w0 > kWaitTicks) {
+                if (wall_clock64() - w0 > wait_ticks) {
                     atomicAdd(timeouts, 1ull);
                     break;
                 }
@@ -206,6 +207,7 @@ struct fft_batch_impl {
     unsigned long long *d_ctr = nullptr;  // BatchCounters, then moved[sum of M_i]
     unsigned long long *d_timeouts = nullptr;  // sticky count of timed-out waits (never reset)
     bool timed_out = false;               // a stats call has seen d_timeouts != 0
+    unsigned long long wait_ticks = kWaitTicks;  // bound of one level wait (real-time clock ticks)
     int64_t nctr = 0;
     std::vector<int> level_task0;         // first task of each level (+ end)
     std::vector<int64_t> level_units;     // units of each level
@@ -257,7 +259,7 @@ int batch_enqueue(fft_batch_impl *b, int dir, hipStream_t s)
     const int nl = (int)b->level_units.size();
 #define FFTRW_LAUNCH(D, T)                                                                                   \
     hipLaunchKernelGGL((batch_kernel<D, T>), dim3(b->grid), dim3(kThreads), b->lds, s, b->d_items, b->d_tasks, \
-                       b->d_level_task0, b->d_level_units, nl, ctr, b->d_timeouts)
+                       b->d_level_task0, b->d_level_units, nl, ctr, b->d_timeouts, b->wait_ticks)
     if (dir < 0) {
         if (b->tw_lds) FFTRW_LAUNCH(-1, true); else FFTRW_LAUNCH(-1, false);
     } else {
@@ -296,6 +298,9 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
     if (!b) return fail(FFTRW_E_NOMEM, "out of host memory");
     b->n = n;
     b->flags = flags;
+    // test hook: FFTRW_BATCH_WAIT_TICKS bounds each level wait (100 MHz
+    // ticks) instead of 2 s, so tests can force the time-out path
+    if (const char *w = std::getenv("FFTRW_BATCH_WAIT_TICKS")) b->wait_ticks = std::strtoull(w, nullptr, 10);
     const unsigned pflags = flags & (FFTRW_FLAG_COUNT_MOVED | FFTRW_FLAG_LEAVE_PERMUTED);
     const bool leave = (flags & FFTRW_FLAG_LEAVE_PERMUTED) != 0;
     b->h_items.resize(n);

@@ -240,7 +240,7 @@ int make_xpose_desc(fft_plan_impl *pl, const Layout &a, const Layout &b, const s
     d->tiles_u = (d->Nu + d->TU - 1) / d->TU;
     d->tiles_v = (d->Nv + d->TV - 1) / d->TV;
     d->tiles_g = (d->nslices + G - 1) / G;
-    if (d->tiles_u * d->tiles_v * d->tiles_g >= (i64)0x7fffffff)
+    if (d->tiles_u * d->tiles_v * d->tiles_g >= (i64)0x7fffffff || d->nslices >= (i64)0x7fffffff)
         return fail(FFTRW_E_SIZE, "array too large for one transpose launch");
     d->count = counter != nullptr;
     d->counter = counter;

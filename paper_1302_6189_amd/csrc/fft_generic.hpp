@@ -28,13 +28,17 @@ __device__ __forceinline__ void stockham_pass(C *row, int N, int Ns, int lanes, 
     constexpr int MAXB = (16 + R - 1) / R;  // N / lanes <= 16 by construction
     const int nbf = N / R;
     const int twstep = N / (Ns * R);
+    // j mod Ns by a multiply: with mg = ceil(2^32 / Ns), floor(j mg / 2^32) =
+    // floor(j / Ns) exactly for j, Ns <= 4096 (the rounding error of mg adds
+    // less than j / 2^32 < 1 / Ns to j / Ns)
+    const uint32_t mg = (uint32_t)(0xffffffffu / (uint32_t)Ns) + 1u;
     C v[MAXB][R];
     int kk[MAXB];
 #pragma unroll
     for (int m = 0; m < MAXB; ++m) {
         const int j = lane + m * lanes;
         if (j < nbf) {
-            const int k = j % Ns;
+            const int k = Ns == 1 ? 0 : j - (int)__umulhi((uint32_t)j, mg) * Ns;
             kk[m] = k;
 #pragma unroll
             for (int i = 0; i < R; ++i) v[m][i] = row[j + i * nbf];

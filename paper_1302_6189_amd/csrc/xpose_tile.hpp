@@ -63,17 +63,21 @@ __device__ __forceinline__ int64_t owner_of_row(int64_t r, int64_t P, int64_t R,
     return ((r + 1) * P - 1) / R;
 }
 
-// coordinates of batch slice s (innermost batch axis first) and its bases
+// coordinates of batch slice s (innermost batch axis first) and its bases;
+// plans keep the slice count below 2^31 (sizes are at most 4096), so 32-bit
+// divisions suffice
 __device__ __forceinline__ void slice_coords(const XposeDesc &d, int64_t s, int *c, int64_t *ab, int64_t *bb)
 {
     int64_t a = 0, b = 0;
+    uint32_t su = (uint32_t)s;
     for (int i = 0; i < d.nbat; ++i) {
-        const int64_t q = s / d.bsize[i];
-        const int64_t ci = s - q * d.bsize[i];
-        s = q;
+        const uint32_t n = (uint32_t)d.bsize[i];
+        const uint32_t q = su / n;
+        const uint32_t ci = su - q * n;
+        su = q;
         c[i] = (int)ci;
-        a += ci * d.ba[i];
-        b += ci * d.bb[i];
+        a += (int64_t)ci * d.ba[i];
+        b += (int64_t)ci * d.bb[i];
     }
     *ab = a;
     *bb = b;

@@ -247,3 +247,29 @@ def test_long_rows_in_a_batch(gpu_lib, flags):
         ref = dft.fftn_direct(xs[i], orders.fft_axis_sequence(order))
         assert dft.rel_l2(to_host(outs[i]), ref) < 1e-5, (i, dims)
         assert st["moved"][i] == st["analytic"][i]
+
+
+def test_barrier_timeout_is_reported(gpu_lib, monkeypatch):
+    # force the time-out path from the host: a level wait bounded by 0 ticks
+    # ends at once, so the batch's results are not reliable -- the sticky
+    # count says so, stats fails with E_DEVICE and the batch refuses to run
+    # again; a batch planned without the hook is unaffected
+    items = [((16, 12, 10, 8), 20), ((20, 18, 24, 6), 7), ((12, 15, 16), 5)] * 8
+    xs = [inputs.uniform(d, 40 + i, np.complex64) for i, (d, _) in enumerate(items)]
+    monkeypatch.setenv("FFTRW_BATCH_WAIT_TICKS", "0")
+    b = fftrw.Batch(items, flags=fftrw.FLAG_COUNT_MOVED)
+    monkeypatch.delenv("FFTRW_BATCH_WAIT_TICKS")
+    ins, outs = _run(b, xs)
+    with pytest.raises(fftrw.FftrwError) as e:
+        b.stats()
+    assert e.value.code == fftrw.E_DEVICE and "timed out" in str(e.value)
+    with pytest.raises(fftrw.FftrwError) as e:
+        b.exec_fwd(ins, outs)
+    assert e.value.code == fftrw.E_DEVICE
+    ok = fftrw.Batch(items, flags=fftrw.FLAG_COUNT_MOVED)
+    _, outs2 = _run(ok, xs)
+    assert ok.stats()["error"] == 0
+    for i, (dims, P) in enumerate(items[:3]):
+        order = fftrw.fft_order_search(dims, P)["best_order"]
+        ref = dft.fftn_direct(xs[i], orders.fft_axis_sequence(order))
+        assert dft.rel_l2(to_host(outs2[i]), ref) < 1e-5
