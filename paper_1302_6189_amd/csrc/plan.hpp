@@ -25,8 +25,10 @@ struct StagedTileCfg {
 struct StagedStep {
     int64_t npair = 0;            // (p, q) pairs that share points
     void *recv_info = nullptr;    // device RecvInfo[P]: destination ranges
-    void *send_info = nullptr;    // device SendInfo[P]: source ranges
-    int nbp = 0, nbq = 0;         // boxes per source / destination range
+    void *lrank = nullptr;        // device int2 per (slice, u) line: rank at v = 0, step per v
+    void *pairs = nullptr;        // device pair table: D(p, q) of every pair, by hash of (p, q)
+    int pair_lg = 0;              // log2 of the pair table's slots
+    int nbq = 0;                  // boxes per destination range
     int64_t nseg = 0;
     void *segs = nullptr;         // device SegCopy[nseg] (p != q only)
     void *chunk_seg = nullptr;    // device int64[2 * chunks]: first/last segment of each exchange chunk

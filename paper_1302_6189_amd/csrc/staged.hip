@@ -36,10 +36,16 @@
 // segment along the innermost axis (in A's order) that a typical (p, q) box
 // spans -- u when q owns long runs of u, otherwise v or a batch axis (for
 // example one value of u and of v but 64 slices per segment).  The plan picks
-// that axis and the tile's extents per transpose.  A tile first computes its
-// owners, then its ranks and pair constants as one independent task per
-// (entry, box), summed with LDS atomics, so the few global loads they need
-// are all in flight together.
+// that axis and the tile's extents per transpose.
+//
+// The plan evaluates both closed forms once, so the tiles only look them up:
+// rank_q at v = 0 and its step per v for every (slice, u) line (a table of
+// T / N_v entries, filled by a kernel when the plan is made), and D(p, q) for
+// every pair that shares points (an open-addressing hash table keyed by
+// (p, q), filled on the host while the pairs are enumerated: per source p,
+// these are the send displacements an all-to-all would take).  A tile computes
+// its owners, numbers its distinct sources and destinations, and fetches the
+// D of its pairs into LDS once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -77,12 +83,17 @@ struct RecvInfo {              // destination q: its range in B
     RankBox box[kRangeBoxes];  // in A's order
 };
 
-struct SendInfo {              // source p: its range in A
-    int64_t xs;                // first point of the range = start of p's send region
-    int first_a[kMaxDims];     // p's first point, coordinates in A's order
+// One slot of the pair table: key p * P + q (-1 = empty), value D(p, q).
+struct PairSlot {
+    int64_t key;
+    int d;
     int pad;
-    RankBox box[kRangeBoxes];  // in B's order
 };
+
+__host__ __device__ inline uint64_t pair_hash(int64_t key, int lg)
+{
+    return ((uint64_t)key * 0x9E3779B97F4A7C15ull) >> (64 - lg);
+}
 
 struct SegCopy {
     int64_t xoff;      // position in the concatenation of exchanged segments
@@ -99,12 +110,14 @@ struct StagedTile {
     int lu, lv, lg;         // log2 of TU, TV, G
     int lane_r, lane_w;
     int M;
-    int nbp, nbq;           // boxes per range in A and in B
+    int nbq;                // boxes per range in B
     int srcpos[kMaxDims];   // per A position: batch index 0..2, 3 = v, 4 = u
     int vpos;               // A position of v
-    int64_t T;
+    int pair_lg;            // log2 of the pair table's slots
+    int64_t T, P;
     const RecvInfo *recv;
-    const SendInfo *send;
+    const int2 *lrank;      // per (slice, u) line: rank_q at v = 0, step per v
+    const PairSlot *pairs;  // D(p, q) of every pair that shares points
 };
 
 struct ExchangeArgs {
@@ -132,22 +145,19 @@ __device__ __forceinline__ int64_t box_rank(const RankBox &B, const int *c, int 
     return r;
 }
 
-// D(p, q), summed box by box (the slow path of tiles with many pairs, in a
-// loop of its own so the common loop stays small)
-__device__ __forceinline__ int64_t pair_base(const StagedTile &a, int p, int q)
+// D(p, q) from the pair table (every pair that owns a point of the array is
+// present; the table is at most half full, so the probe ends at a free slot)
+__device__ __forceinline__ int pair_offset(const StagedTile &a, int p, int q)
 {
-    const SendInfo &S = a.send[p];
-    const RecvInfo &R = a.recv[q];
-    int64_t r = S.xs;
-    for (int j = 0; j < a.nbp; ++j) {
-        const RankBox B = S.box[j];
-        r += box_rank(B, R.first_b, a.M);
+    const int64_t key = (int64_t)p * a.P + q;
+    const uint64_t mask = ((uint64_t)1 << a.pair_lg) - 1;
+    uint64_t h = pair_hash(key, a.pair_lg);
+    for (uint64_t n = 0; n <= mask; ++n, h = (h + 1) & mask) {
+        const int64_t k = a.pairs[h].key;
+        if (k == key) return a.pairs[h].d;
+        if (k < 0) break;
     }
-    for (int j = 0; j < a.nbq; ++j) {
-        const RankBox B = R.box[j];
-        r -= box_rank(B, S.first_a, a.M);
-    }
-    return r;
+    return INT_MIN / 2;  // no such pair: the offset falls outside the array and is not written
 }
 
 constexpr int kPairTab = 1024;  // dense (p, q) constants per pack tile
@@ -203,7 +213,12 @@ __host__ __device__ inline TileLds tile_lds(int lu, int lv, int lg, size_t esz, 
         o = (o + bytes + 15) & ~(size_t)15;
         return at;
     };
-    L.tile = take(G * SG * esz);
+    // a pack tile's owner hash (keys, numbers, lists for p and q) lives only
+    // until the owners are renumbered, before any value reaches the tile, so
+    // the two share their LDS
+    const size_t hash_bytes = 6 * kOwnHash * 4;
+    const size_t tile_bytes = G * SG * esz;
+    L.tile = take(pack && hash_bytes > tile_bytes ? hash_bytes : tile_bytes);
     L.gbase = take(G * 4);
     L.gc = take(G * 3 * 4);
     L.r0 = take(G * TU * 4);
@@ -215,15 +230,10 @@ __host__ __device__ inline TileLds tile_lds(int lu, int lv, int lg, size_t esz, 
     L.pt = pack ? take(kPairTab * 4) : 0;
     L.own_a = take(G * TV * 4);
     L.own_b = take(G * TU * 4);
-    L.hash = pack ? take(6 * kOwnHash * 4) : 0;  // keys, numbers, lists for p and q
+    L.hash = L.tile;
     L.misc = take(16);
     L.total = o;
     return L;
-}
-
-__device__ __forceinline__ void lds_add(int *p, int64_t v)
-{
-    if (v) atomicAdd(p, (int)v);
 }
 
 // One pass over a tile with axis LANE fastest across lanes: thread t owns lane
@@ -308,7 +318,7 @@ __global__ void __launch_bounds__(kThreads)
     }
     if (PACK)
         for (int i = threadIdx.x; i < 2 * kOwnHash; i += kThreads) hk[i] = -1;
-    // each slice's coordinates once (64-bit divisions), then owners from them
+    // each slice's coordinates once, then owners from them
     for (int g = threadIdx.x; g < ng; g += kThreads) {
         int c[3] = {0, 0, 0};
         int64_t ab, bb;
@@ -318,13 +328,34 @@ __global__ void __launch_bounds__(kThreads)
         gc[3 * g + 1] = c[1];
         gc[3 * g + 2] = c[2];
     }
-    for (int i = threadIdx.x; i < G * TU; i += kThreads) {
-        r0[i] = 0;
-        wv[i] = 0;
-    }
-    if (PACK)
-        for (int i = threadIdx.x; i < kPairTab; i += kThreads) pt[i] = 0;
     __syncthreads();
+    // a pack tile issues the loads that need no owner now and consumes them
+    // after the owner arithmetic: its line-table entries (a tile has at most
+    // 512 (slice, u) lines) and its values (A's addresses depend only on the
+    // slice bases).  (Unpack tiles load their line entries with q's constants:
+    // issued early as well, the return transpose's unpack at 512^3 went from
+    // 0.42 to 0.63 ms.)
+    const int nlines = ng * nu;
+    int2 lr[2];
+    C val[kTileItems];
+    int at[kTileItems];
+#pragma unroll
+    for (int j = 0; j < kTileItems; ++j) at[j] = -1;
+    if constexpr (PACK) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int i = threadIdx.x + j * kThreads;
+            if (i < nlines) {
+                const int g = i / nu, iu = i - g * nu;
+                lr[j] = a.lrank[(g0 + g) * d.Nu + u0 + iu];
+            }
+        }
+        const int a_sv = (int)d.a_sv;
+        tile_pass<LR>(lu, lv, lg, nu, nv, ng, [&](int j, int g, int iv, int iu) {
+            at[j] = g * SG + iv * SV + iu;
+            val[j] = xld(src + (gbase[g] + (int)(v0 + iv) * a_sv + (int)u0 + iu));
+        });
+    }
     {
         // below level M, A's leading axes are batch axes and v, B's are batch
         // axes and u (the staged path refuses level M)
@@ -350,38 +381,24 @@ __global__ void __launch_bounds__(kThreads)
     }
     __syncthreads();
 
-    // ranks per (slice, u): one task per (entry, box of q's range); unpack also
-    // picks up q's constants, pack the span of owners in the tile
-    const int per_e = a.nbq + (PACK ? 0 : 1);
-    const int ntask = ng * nu * per_e;
-    for (int i = threadIdx.x; i < ntask; i += kThreads) {
-        const int e = i / per_e;
-        const int j = i - e * per_e;
-        const int g = e / nu, iu = e - g * nu;
+    // per (slice, u) line: rank_q at the tile's first v and its step per v;
+    // unpack also picks up q's constants
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int i = threadIdx.x + j * kThreads;
+        if (i >= nlines) break;
+        const int g = i / nu, iu = i - g * nu;
         const int k = g * TU + iu;
-        const RecvInfo &R = a.recv[own_b[k]];
-        if (j == a.nbq) {
+        if (!PACK) lr[j] = a.lrank[(g0 + g) * d.Nu + u0 + iu];
+        r0[k] = lr[j].x + (int)v0 * lr[j].y;
+        wv[k] = lr[j].y;
+        if (!PACK) {
+            const RecvInfo &R = a.recv[own_b[k]];
             rb[k] = (int)R.start;
             sb[k] = (int)R.selfbase;
             kp[k] = (int)R.kept;
             ks[k] = R.ksrc;
-            continue;
         }
-        const int *bc = gc + 3 * g;
-        int c[kMaxDims];
-#pragma unroll
-        for (int m = 0; m < kMaxDims; ++m) {
-            const int sp = a.srcpos[m];
-            c[m] = sp == 3 ? (int)v0 : sp == 4 ? (int)(u0 + iu) : sp == 0 ? bc[0] : sp == 1 ? bc[1] : bc[2];
-        }
-        const RankBox B = R.box[j];
-        const int64_t ra = box_rank(B, c, M);
-#pragma unroll
-        for (int m = 0; m < kMaxDims; ++m)
-            if (m == a.vpos) c[m] += 1;
-        const int64_t rn = box_rank(B, c, M);
-        lds_add(&r0[k], ra);
-        lds_add(&wv[k], rn - ra);
     }
     if (PACK) {
         // number the tile's distinct owners densely, p (A) and q (B) apart
@@ -392,30 +409,13 @@ __global__ void __launch_bounds__(kThreads)
     }
     __syncthreads();
 
-    // pack: D(p, q) for every pair of the tile's distinct owners, one task per
-    // (pair, box) plus one for xs_p; the owner tables then hold dense numbers
+    // pack: D(p, q) of every pair of the tile's distinct owners (pairs that
+    // share no point look up nothing usable and are never read); the owner
+    // tables then hold dense numbers
     const int np = PACK ? mm[0] : 0, nq = PACK ? mm[1] : 0;
     const bool dense = PACK && mm[2] == 0 && np * nq <= kPairTab;
     if (PACK && dense) {
-        const int per = a.nbp + a.nbq + 1;
-        const int n = np * nq * per;
-        for (int i = threadIdx.x; i < n; i += kThreads) {
-            const int e = i / per, j = i - e * per;
-            const int p = hl[e / nq], q = hl[kOwnHash + e % nq];
-            const SendInfo &S = a.send[p];
-            const RecvInfo &R = a.recv[q];
-            int64_t v;
-            if (j < a.nbp) {
-                const RankBox B = S.box[j];
-                v = box_rank(B, R.first_b, M);
-            } else if (j < a.nbp + a.nbq) {
-                const RankBox B = R.box[j - a.nbp];
-                v = -box_rank(B, S.first_a, M);
-            } else {
-                v = S.xs;
-            }
-            lds_add(&pt[e], v);
-        }
+        for (int e = threadIdx.x; e < np * nq; e += kThreads) pt[e] = pair_offset(a, hl[e / nq], hl[kOwnHash + e % nq]);
         for (int i = threadIdx.x; i < ng * nv; i += kThreads) {
             int &o = own_a[(i / nv) * TV + i % nv];
             o = own_lookup(hk, hn, o);
@@ -427,38 +427,29 @@ __global__ void __launch_bounds__(kThreads)
         __syncthreads();
     }
 
-    // read: every item's load is issued before any LDS store
-    {
-        C val[kTileItems];
-        int at[kTileItems];
-#pragma unroll
-        for (int j = 0; j < kTileItems; ++j) at[j] = -1;
-        const int a_sv = (int)d.a_sv;
+    // unpack reads (every item's load is issued before any LDS store), then
+    // the values into the tile
+    if constexpr (!PACK) {
         tile_pass<LR>(lu, lv, lg, nu, nv, ng, [&](int j, int g, int iv, int iu) {
             at[j] = g * SG + iv * SV + iu;
-            if (PACK) {
-                val[j] = xld(src + (gbase[g] + (int)(v0 + iv) * a_sv + (int)u0 + iu));
+            const int k = g * TU + iu;
+            const int p = own_a[g * TV + iv];
+            const int rk = r0[k] + iv * wv[k];
+            const C *from = src;
+            int off;
+            const int keep_src = ks[k];
+            if (p == keep_src) {
+                from = self_src;
+                off = sb[k] + rk;
             } else {
-                const int k = g * TU + iu;
-                const int p = own_a[g * TV + iv];
-                const int q = own_b[k];
-                const int rk = r0[k] + iv * wv[k];
-                const C *from = src;
-                int off;
-                const int keep_src = ks[k];
-                if (p == keep_src) {
-                    from = self_src;
-                    off = sb[k] + rk;
-                } else {
-                    off = rb[k] + rk - (p > keep_src ? kp[k] : 0);
-                }
-                val[j] = (uint32_t)off < (uint32_t)a.T ? xld(from + off) : mk<C>(0, 0);
+                off = rb[k] + rk - (p > keep_src ? kp[k] : 0);
             }
+            val[j] = (uint32_t)off < (uint32_t)a.T ? xld(from + off) : mk<C>(0, 0);
         });
-#pragma unroll
-        for (int j = 0; j < kTileItems; ++j)
-            if (at[j] >= 0) tile[at[j]] = val[j];
     }
+#pragma unroll
+    for (int j = 0; j < kTileItems; ++j)
+        if (at[j] >= 0) tile[at[j]] = val[j];
     __syncthreads();
     // write
     if (PACK) {
@@ -471,7 +462,7 @@ __global__ void __launch_bounds__(kThreads)
         } else {
             tile_pass<LW>(lu, lv, lg, nu, nv, ng, [&](int, int g, int iv, int iu) {
                 const int k = g * TU + iu;
-                const int off = (int)pair_base(a, own_a[g * TV + iv], own_b[k]) + r0[k] + iv * wv[k];
+                const int off = pair_offset(a, own_a[g * TV + iv], own_b[k]) + r0[k] + iv * wv[k];
                 if ((uint32_t)off < (uint32_t)a.T) xst(dst + off, tile[g * SG + iv * SV + iu]);
             });
         }
@@ -480,6 +471,39 @@ __global__ void __launch_bounds__(kThreads)
         tile_pass<LW>(lu, lv, lg, nu, nv, ng, [&](int, int g, int iv, int iu) {
             xst(dst + (gbase[g] + (int)(u0 + iu) * b_su + (int)v0 + iv), tile[g * SG + iv * SV + iu]);
         });
+    }
+}
+
+// Plan time: for every (slice, u) line, in the slice numbering of the tiles,
+// rank_q of its point at v = 0 and the step of rank_q per unit of v (q = the
+// line's owner in B).  q's boxes span all of v, so rank_q is affine in v.
+__global__ void __launch_bounds__(kThreads) staged_rank_kernel(StagedTile a, int2 *__restrict__ out)
+{
+    const XposeDesc &d = a.d;
+    const int64_t n = d.nslices * d.Nu;
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+        const int64_t sl = x / d.Nu;
+        const int u = (int)(x - sl * d.Nu);
+        int bc[3] = {0, 0, 0};
+        int64_t ab, bb;
+        slice_coords(d, sl, bc, &ab, &bb);
+        int64_t r = 0;
+        for (int j = 0; j < d.kb; ++j) {
+            const int src = d.srcb[j];
+            r += (src == 4 ? (int64_t)u : (int64_t)bc[src]) * d.wb[j];
+        }
+        const RecvInfo &R = a.recv[owner_of_row(r, d.P, d.Rb, d.owner32 != 0)];
+        int c[kMaxDims];
+#pragma unroll
+        for (int m = 0; m < kMaxDims; ++m) {
+            const int sp = a.srcpos[m];
+            c[m] = sp == 3 ? 0 : sp == 4 ? u : bc[sp < 3 ? sp : 0];
+        }
+        int64_t ra = 0, rn = 0;
+        for (int j = 0; j < a.nbq; ++j) ra += box_rank(R.box[j], c, a.M);
+        c[a.vpos] += 1;
+        for (int j = 0; j < a.nbq; ++j) rn += box_rank(R.box[j], c, a.M);
+        out[x] = make_int2((int)ra, (int)(rn - ra));
     }
 }
 
@@ -802,7 +826,8 @@ int staged_build(fft_plan_impl *pl, int t)
         ri[mu[p]].kept = 0;
         ri[mu[p]].selfbase = 0;
     }
-    std::vector<SendInfo> si(P);
+    std::vector<PairSlot> pd;          // (p * P + q, D(p, q)) of every pair
+    pd.reserve(pc.size());
     std::vector<i64> before_q(P, 0);   // points of Q_q in the ranges of sources < p
     std::vector<i64> recv_fill(P, 0);  // received points of q so far (sources other than ksrc)
     std::vector<SegCopy> segs;
@@ -814,9 +839,11 @@ int staged_build(fft_plan_impl *pl, int t)
             i64 segoff = 0;
             for (; i < pc.size() && pc[i].p == p; ++i) {
                 const i64 q = pc[i].q, n = pc[i].n;
+                const i64 D = xs + segoff - before_q[q];
+                pd.push_back({p * P + q, (int)D, 0});
                 if (q == mu[p]) {
                     ri[q].kept = n;
-                    ri[q].selfbase = xs + segoff - before_q[q];
+                    ri[q].selfbase = D;
                 } else {
                     segs.push_back({moved, xs + segoff, b.boundary(q) + recv_fill[q], n});
                     moved += n;
@@ -829,8 +856,8 @@ int staged_build(fft_plan_impl *pl, int t)
                 return fail(FFTRW_E_DEVICE, "internal: staged pairs do not cover a range");
         }
     }
-    // ranges as boxes: destinations in A's order, sources in B's order
-    int nbp = 0, nbq = 0;
+    // destination ranges as boxes in A's order
+    int nbq = 0;
     for (i64 q = 0; q < P; ++q) {
         RecvInfo &r = ri[q];
         r.start = b.boundary(q);
@@ -842,25 +869,25 @@ int staged_build(fft_plan_impl *pl, int t)
         nbq = std::max(nbq, (int)boxes.size());
         fill_boxes(boxes, a.perm, M, r.box);
     }
-    for (i64 p = 0; p < P; ++p) {
-        SendInfo &s = si[p];
-        s.xs = a.boundary(p);
-        i64 st[kMaxDims];
-        range_of(a, p, nullptr, nullptr, st, nullptr);
-        for (int i = 0; i < kMaxDims; ++i) s.first_a[i] = i < M ? (int)st[i] : 0;
-        s.pad = 0;
-        const std::vector<Box> boxes = range_boxes(a, p);
-        if ((int)boxes.size() > kRangeBoxes) return fail(FFTRW_E_DEVICE, "internal: too many range boxes");
-        nbp = std::max(nbp, (int)boxes.size());
-        fill_boxes(boxes, b.perm, M, s.box);
+    // the pair table, at most half full
+    int lg = 4;
+    while (((size_t)1 << lg) < 2 * pd.size()) ++lg;
+    std::vector<PairSlot> tab((size_t)1 << lg, PairSlot{-1, 0, 0});
+    {
+        const uint64_t mask = ((uint64_t)1 << lg) - 1;
+        for (const PairSlot &e : pd) {
+            uint64_t h = pair_hash(e.key, lg);
+            while (tab[h].key >= 0) h = (h + 1) & mask;
+            tab[h] = e;
+        }
     }
 
     StagedStep &st = pl->staged[t];
     st.npair = (int64_t)pc.size();
     st.nseg = (int64_t)segs.size();
     st.seg_elems = moved;
-    st.nbp = nbp;
     st.nbq = nbq;
+    st.pair_lg = lg;
     st.seg_axis = segment_axis(a, b, M);
     st.pack = make_tile(pl, t, st.seg_axis, true);
     st.unpack = make_tile(pl, t, st.seg_axis, false);
@@ -869,6 +896,14 @@ int staged_build(fft_plan_impl *pl, int t)
             return fail(FFTRW_E_SIZE, "array too large for one staged launch");
         if (c->lu + c->lv + c->lg > 12 || c->lu + c->lg > 9 || c->lu > 8 || c->lv > 8 || c->lg > 8)
             return fail(FFTRW_E_DEVICE, "internal: staged tile exceeds its LDS tables");
+    }
+    // pack and unpack index the line table by the same slice numbering
+    {
+        const XposeDesc &x = st.pack.d, &y = st.unpack.d;
+        bool same = x.nbat == y.nbat && x.nslices == y.nslices && x.Nu == y.Nu;
+        for (int i = 0; i < x.nbat; ++i) same = same && x.bsize[i] == y.bsize[i];
+        for (int i = 0; i < kMaxDims; ++i) same = same && st.pack.srcpos[i] == st.unpack.srcpos[i];
+        if (!same) return fail(FFTRW_E_DEVICE, "internal: staged tilings number slices differently");
     }
     // first and last segment of every exchange chunk
     std::vector<int64_t> chunk_seg;
@@ -886,10 +921,29 @@ int staged_build(fft_plan_impl *pl, int t)
         }
     }
     int rc = copy_to_device(pl, ri.data(), sizeof(RecvInfo) * ri.size(), &st.recv_info);
-    if (!rc) rc = copy_to_device(pl, si.data(), sizeof(SendInfo) * si.size(), &st.send_info);
+    if (!rc) rc = copy_to_device(pl, tab.data(), sizeof(PairSlot) * tab.size(), &st.pairs);
     if (!rc) rc = copy_to_device(pl, segs.data(), sizeof(SegCopy) * segs.size(), &st.segs);
     if (!rc) rc = copy_to_device(pl, chunk_seg.data(), sizeof(int64_t) * chunk_seg.size(), &st.chunk_seg);
-    return rc;
+    if (!rc) rc = copy_to_device(pl, nullptr, sizeof(int2) * (size_t)(st.pack.d.nslices * st.pack.d.Nu), &st.lrank);
+    if (rc) return rc;
+    // the line table, once per plan
+    StagedTile g;
+    std::memset(&g, 0, sizeof(g));
+    g.d = st.pack.d;
+    g.M = M;
+    g.nbq = nbq;
+    for (int i = 0; i < kMaxDims; ++i) g.srcpos[i] = st.pack.srcpos[i];
+    g.vpos = st.pack.vpos;
+    g.T = pl->T;
+    g.P = P;
+    g.recv = (const RecvInfo *)st.recv_info;
+    const int64_t lines = g.d.nslices * g.d.Nu;
+    const int64_t blocks = std::min<int64_t>((lines + kThreads - 1) / kThreads, 65536);
+    hipLaunchKernelGGL(staged_rank_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, nullptr, g, (int2 *)st.lrank);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return fail(FFTRW_E_DEVICE, std::string("staged line table: ") + hipGetErrorString(e));
+    return FFTRW_OK;
 }
 
 namespace {
@@ -905,13 +959,15 @@ StagedTile tile_args(const fft_plan_impl *pl, const StagedStep &st, const Staged
     g.lane_r = c.lane_r;
     g.lane_w = c.lane_w;
     g.M = pl->M;
-    g.nbp = st.nbp;
     g.nbq = st.nbq;
     for (int i = 0; i < kMaxDims; ++i) g.srcpos[i] = c.srcpos[i];
     g.vpos = c.vpos;
+    g.pair_lg = st.pair_lg;
     g.T = pl->T;
+    g.P = pl->P;
     g.recv = (const RecvInfo *)st.recv_info;
-    g.send = (const SendInfo *)st.send_info;
+    g.lrank = (const int2 *)st.lrank;
+    g.pairs = (const PairSlot *)st.pairs;
     return g;
 }
 
@@ -983,7 +1039,7 @@ int staged_run(fft_plan_impl *pl, int t, const void *in, void *out, hipStream_t 
 void staged_free(fft_plan_impl *pl)
 {
     for (StagedStep &st : pl->staged) {
-        for (void *p : {st.recv_info, st.send_info, st.segs, st.chunk_seg})
+        for (void *p : {st.recv_info, st.lrank, st.pairs, st.segs, st.chunk_seg})
             if (p) (void)hipFree(p);
         st = StagedStep{};
     }
