@@ -221,15 +221,15 @@ __host__ __device__ inline TileLds tile_lds(int lu, int lv, int lg, size_t esz, 
     L.tile = take(pack && hash_bytes > tile_bytes ? hash_bytes : tile_bytes);
     L.gbase = take(G * 4);
     L.gc = take(G * 3 * 4);
-    L.r0 = take(G * TU * 4);
-    L.wv = take(G * TU * 4);
-    L.rb = pack ? 0 : take(G * TU * 4);
-    L.sb = pack ? 0 : take(G * TU * 4);
-    L.kp = pack ? 0 : take(G * TU * 4);
-    L.ks = pack ? 0 : take(G * TU * 4);
+    L.r0 = take(G * (TU + 1) * 4);
+    L.wv = take(G * (TU + 1) * 4);
+    L.rb = pack ? 0 : take(G * (TU + 1) * 4);
+    L.sb = pack ? 0 : take(G * (TU + 1) * 4);
+    L.kp = pack ? 0 : take(G * (TU + 1) * 4);
+    L.ks = pack ? 0 : take(G * (TU + 1) * 4);
     L.pt = pack ? take(kPairTab * 4) : 0;
-    L.own_a = take(G * TV * 4);
-    L.own_b = take(G * TU * 4);
+    L.own_a = take(G * (TV + 1) * 4);
+    L.own_b = take(G * (TU + 1) * 4);
     L.hash = L.tile;
     L.misc = take(16);
     L.total = o;
@@ -281,6 +281,10 @@ __global__ void __launch_bounds__(kThreads)
     const int lu = a.lu, lv = a.lv, lg = a.lg;
     const int TU = 1 << lu, TV = 1 << lv, G = 1 << lg;
     const int SV = TU + 1, SG = TV * SV + 1;
+    // per-line tables (owners, ranks, q's constants) are padded by one entry
+    // per slice: a pass with lanes along the slices then reads them from
+    // different banks (a stride of TU = 16 put every fourth slice on one)
+    const int KU = TU + 1, KV = TV + 1;
     const int M = a.M;
     uint32_t t = blockIdx.x;
     const uint32_t tu = t % (uint32_t)d.tiles_u;
@@ -367,7 +371,7 @@ __global__ void __launch_bounds__(kThreads)
                 const int src = d.srca[j];
                 r += (src == 3 ? v0 + iv : (int64_t)gc[3 * g + src]) * d.wa[j];
             }
-            own_a[g * TV + iv] = (int)owner_of_row(r, d.P, d.Ra, narrow);
+            own_a[g * KV + iv] = (int)owner_of_row(r, d.P, d.Ra, narrow);
         }
         for (int i = threadIdx.x; i < ng * nu; i += kThreads) {
             const int g = i / nu, iu = i - g * nu;
@@ -376,7 +380,7 @@ __global__ void __launch_bounds__(kThreads)
                 const int src = d.srcb[j];
                 r += (src == 4 ? u0 + iu : (int64_t)gc[3 * g + src]) * d.wb[j];
             }
-            own_b[g * TU + iu] = (int)owner_of_row(r, d.P, d.Rb, narrow);
+            own_b[g * KU + iu] = (int)owner_of_row(r, d.P, d.Rb, narrow);
         }
     }
     __syncthreads();
@@ -388,7 +392,7 @@ __global__ void __launch_bounds__(kThreads)
         const int i = threadIdx.x + j * kThreads;
         if (i >= nlines) break;
         const int g = i / nu, iu = i - g * nu;
-        const int k = g * TU + iu;
+        const int k = g * KU + iu;
         if (!PACK) lr[j] = a.lrank[(g0 + g) * d.Nu + u0 + iu];
         r0[k] = lr[j].x + (int)v0 * lr[j].y;
         wv[k] = lr[j].y;
@@ -403,9 +407,9 @@ __global__ void __launch_bounds__(kThreads)
     if (PACK) {
         // number the tile's distinct owners densely, p (A) and q (B) apart
         for (int i = threadIdx.x; i < ng * nv; i += kThreads)
-            own_insert(hk, hn, hl, &mm[0], &mm[2], own_a[(i / nv) * TV + i % nv]);
+            own_insert(hk, hn, hl, &mm[0], &mm[2], own_a[(i / nv) * KV + i % nv]);
         for (int i = threadIdx.x; i < ng * nu; i += kThreads)
-            own_insert(hk + kOwnHash, hn + kOwnHash, hl + kOwnHash, &mm[1], &mm[2], own_b[(i / nu) * TU + i % nu]);
+            own_insert(hk + kOwnHash, hn + kOwnHash, hl + kOwnHash, &mm[1], &mm[2], own_b[(i / nu) * KU + i % nu]);
     }
     __syncthreads();
 
@@ -417,11 +421,11 @@ __global__ void __launch_bounds__(kThreads)
     if (PACK && dense) {
         for (int e = threadIdx.x; e < np * nq; e += kThreads) pt[e] = pair_offset(a, hl[e / nq], hl[kOwnHash + e % nq]);
         for (int i = threadIdx.x; i < ng * nv; i += kThreads) {
-            int &o = own_a[(i / nv) * TV + i % nv];
+            int &o = own_a[(i / nv) * KV + i % nv];
             o = own_lookup(hk, hn, o);
         }
         for (int i = threadIdx.x; i < ng * nu; i += kThreads) {
-            int &o = own_b[(i / nu) * TU + i % nu];
+            int &o = own_b[(i / nu) * KU + i % nu];
             o = own_lookup(hk + kOwnHash, hn + kOwnHash, o);
         }
         __syncthreads();
@@ -432,8 +436,8 @@ __global__ void __launch_bounds__(kThreads)
     if constexpr (!PACK) {
         tile_pass<LR>(lu, lv, lg, nu, nv, ng, [&](int j, int g, int iv, int iu) {
             at[j] = g * SG + iv * SV + iu;
-            const int k = g * TU + iu;
-            const int p = own_a[g * TV + iv];
+            const int k = g * KU + iu;
+            const int p = own_a[g * KV + iv];
             const int rk = r0[k] + iv * wv[k];
             const C *from = src;
             int off;
@@ -455,14 +459,14 @@ __global__ void __launch_bounds__(kThreads)
     if (PACK) {
         if (dense) {
             tile_pass<LW>(lu, lv, lg, nu, nv, ng, [&](int, int g, int iv, int iu) {
-                const int k = g * TU + iu;
-                const int off = pt[own_a[g * TV + iv] * nq + own_b[k]] + r0[k] + iv * wv[k];
+                const int k = g * KU + iu;
+                const int off = pt[own_a[g * KV + iv] * nq + own_b[k]] + r0[k] + iv * wv[k];
                 if ((uint32_t)off < (uint32_t)a.T) xst(dst + off, tile[g * SG + iv * SV + iu]);
             });
         } else {
             tile_pass<LW>(lu, lv, lg, nu, nv, ng, [&](int, int g, int iv, int iu) {
-                const int k = g * TU + iu;
-                const int off = pair_offset(a, own_a[g * TV + iv], own_b[k]) + r0[k] + iv * wv[k];
+                const int k = g * KU + iu;
+                const int off = pair_offset(a, own_a[g * KV + iv], own_b[k]) + r0[k] + iv * wv[k];
                 if ((uint32_t)off < (uint32_t)a.T) xst(dst + off, tile[g * SG + iv * SV + iu]);
             });
         }
