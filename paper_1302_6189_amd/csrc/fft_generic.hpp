@@ -22,8 +22,21 @@ namespace fftrw {
 // Pass with radix R after sub-transforms of size Ns: butterfly j (< N/R) reads
 // x[j + i N/R], multiplies by w_{Ns R}^{i k} (k = j mod Ns), runs DFT_R and
 // writes y[(j - k) R + k + i Ns].
+// Synchronisation between a pass's reads and writes: the row's own lanes only
+// when they all sit in one wave (wave = true), else the whole work-group.
+__device__ __forceinline__ void row_sync(bool wave)
+{
+    if (wave) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 template <int R, int DIR, typename C>
-__device__ __forceinline__ void stockham_pass(C *row, int N, int Ns, int lanes, int lane, const C *tw)
+__device__ __forceinline__ void stockham_pass(C *row, int N, int Ns, int lanes, int lane, const C *tw, bool wave)
 {
     constexpr int MAXB = (16 + R - 1) / R;  // N / lanes <= 16 by construction
     const int nbf = N / R;
@@ -49,7 +62,7 @@ __device__ __forceinline__ void stockham_pass(C *row, int N, int Ns, int lanes, 
             Dft<R, DIR, C>::run(v[m]);
         }
     }
-    __syncthreads();
+    row_sync(wave);
 #pragma unroll
     for (int m = 0; m < MAXB; ++m) {
         const int j = lane + m * lanes;
@@ -60,7 +73,7 @@ __device__ __forceinline__ void stockham_pass(C *row, int N, int Ns, int lanes, 
             for (int i = 0; i < R; ++i) row[base + i * Ns] = v[m][i];
         }
     }
-    __syncthreads();
+    row_sync(wave);
 }
 
 // Copies cnt values into LDS; each thread issues up to kLoadBatch loads before
@@ -156,19 +169,24 @@ __device__ __forceinline__ void fft_rows_block(const C *in, C *out, const FftDes
     const int lane = threadIdx.x - row * lanes;
     C *lrow = lds + row * N;
     const C *tw = TW_LDS ? static_cast<const C *>(ltw) : reinterpret_cast<const C *>(d.tw);
+    // a row's lanes are consecutive threads, a power of two of them: at most
+    // 64 sit in one wave, and the passes then synchronise that wave only (the
+    // stores read across rows and wait for the whole group)
+    const bool wave = lanes <= 64;
     int Ns = 1;
     for (int p = 0; p < d.npass; ++p) {
         switch (d.radix[p]) {
-        case 2: stockham_pass<2, DIR>(lrow, N, Ns, lanes, lane, tw); break;
-        case 3: stockham_pass<3, DIR>(lrow, N, Ns, lanes, lane, tw); break;
-        case 4: stockham_pass<4, DIR>(lrow, N, Ns, lanes, lane, tw); break;
-        case 5: stockham_pass<5, DIR>(lrow, N, Ns, lanes, lane, tw); break;
-        case 8: stockham_pass<8, DIR>(lrow, N, Ns, lanes, lane, tw); break;
-        case 16: stockham_pass<16, DIR>(lrow, N, Ns, lanes, lane, tw); break;
+        case 2: stockham_pass<2, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
+        case 3: stockham_pass<3, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
+        case 4: stockham_pass<4, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
+        case 5: stockham_pass<5, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
+        case 8: stockham_pass<8, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
+        case 16: stockham_pass<16, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
         default: break;
         }
         Ns *= d.radix[p];
     }
+    if (wave) __syncthreads();
     store_block(out + row0 * N, lds, cnt, scale, do_scale);
     __syncthreads();  // the LDS block may be reused by the caller's next unit
 }

@@ -227,19 +227,24 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
     const int lane = threadIdx.x - row * lanes;
     C *lrow = lds + row * S;
     const C *tw = TW_LDS ? static_cast<const C *>(ltw) : reinterpret_cast<const C *>(f.tw);
+    // a row's lanes are consecutive threads, a power of two of them: at most
+    // 64 sit in one wave, and the passes then synchronise that wave only (the
+    // stores read across rows and wait for the whole group)
+    const bool wave = lanes <= 64;
     int Ns = 1;
     for (int p = 0; p < f.npass; ++p) {
         switch (f.radix[p]) {
-        case 2: stockham_pass<2, DIR>(lrow, N, Ns, lanes, lane, tw); break;
-        case 3: stockham_pass<3, DIR>(lrow, N, Ns, lanes, lane, tw); break;
-        case 4: stockham_pass<4, DIR>(lrow, N, Ns, lanes, lane, tw); break;
-        case 5: stockham_pass<5, DIR>(lrow, N, Ns, lanes, lane, tw); break;
-        case 8: stockham_pass<8, DIR>(lrow, N, Ns, lanes, lane, tw); break;
-        case 16: stockham_pass<16, DIR>(lrow, N, Ns, lanes, lane, tw); break;
+        case 2: stockham_pass<2, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
+        case 3: stockham_pass<3, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
+        case 4: stockham_pass<4, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
+        case 5: stockham_pass<5, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
+        case 8: stockham_pass<8, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
+        case 16: stockham_pass<16, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
         default: break;
         }
         Ns *= f.radix[p];
     }
+    if (wave) __syncthreads();
     // frequency k of row (gi, r) goes to B at (slice g0 + gi, u = k, v = v0 + r),
     // runs of nv consecutive v; 16-byte pairs of v when N_v and rw are even
     // (complex64: every run then starts on an even element)
