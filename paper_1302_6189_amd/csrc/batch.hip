@@ -85,8 +85,11 @@ __device__ __forceinline__ float2 *batch_buf(const BatchItemDev &it, int kind)
 // The inverse (whose last stage also scales) is held to three waves per SIMD
 // (at most 168 VGPRs; it needs one more otherwise, which would leave two).
 // The forward fits without the hint and runs 1% faster without it.
-template <int DIR, bool TW_LDS>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(DIR > 0 ? 3 : 1)))
+// LEAN: every stage of every item is a fused unit with radices 2, 3, 4 and 5
+// only; without the other stage kernels and the larger passes the kernel
+// fits four waves per SIMD.
+template <int DIR, bool TW_LDS, bool LEAN>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LEAN ? 4 : (DIR > 0 ? 3 : 1))))
     batch_kernel(const BatchItemDev *__restrict__ items, const BatchTask *__restrict__ tasks,
                  const int *__restrict__ level_task0, const int64_t *__restrict__ level_units, int nlevels,
                  BatchCounters *ctr, unsigned long long *timeouts, unsigned long long wait_ticks)
@@ -138,6 +141,12 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(D
             const int st = tk.stage;
             const float2 *src = batch_buf(it, it.src[st]);
             float2 *dst = batch_buf(it, it.dst[st]);
+            if constexpr (LEAN) {
+                const bool last = st == it.M - 1;
+                fft_xpose_unit<float2, DIR, TW_LDS, true>(src, dst, it.fft[st], it.xp[st], it.frw[st], it.fg[st], local,
+                                                          DIR > 0 && last ? it.inv_scale : 1.f, DIR > 0 && last, smem);
+                continue;
+            }
             if (it.fused) {
                 const bool last = st == it.M - 1;
                 const float sc = DIR > 0 && last ? it.inv_scale : 1.f;
@@ -227,6 +236,7 @@ struct fft_batch_impl {
     bool tuned = false;  // a matching autotuner cache was applied
     bool any_fused = false;
     bool tw_lds = false;  // fused units stage their twiddle tables in LDS
+    bool lean = false;    // every stage a fused unit of radices 2..5 (batch_kernel's LEAN form)
 };
 
 namespace {
@@ -260,13 +270,21 @@ int batch_enqueue(fft_batch_impl *b, int dir, hipStream_t s)
     if (e != hipSuccess) return batch_fail_hip(e, "batch reset launch");
     BatchCounters *ctr = reinterpret_cast<BatchCounters *>(b->d_ctr);
     const int nl = (int)b->level_units.size();
-#define FFTRW_LAUNCH(D, T)                                                                                   \
-    hipLaunchKernelGGL((batch_kernel<D, T>), dim3(b->grid), dim3(kThreads), b->lds, s, b->d_items, b->d_tasks, \
+#define FFTRW_LAUNCH(D, T, L)                                                                                   \
+    hipLaunchKernelGGL((batch_kernel<D, T, L>), dim3(b->grid), dim3(kThreads), b->lds, s, b->d_items, b->d_tasks, \
                        b->d_level_task0, b->d_level_units, nl, ctr, b->d_timeouts, b->wait_ticks)
-    if (dir < 0) {
-        if (b->tw_lds) FFTRW_LAUNCH(-1, true); else FFTRW_LAUNCH(-1, false);
+    if (b->lean) {
+        if (dir < 0) {
+            if (b->tw_lds) FFTRW_LAUNCH(-1, true, true); else FFTRW_LAUNCH(-1, false, true);
+        } else {
+            if (b->tw_lds) FFTRW_LAUNCH(1, true, true); else FFTRW_LAUNCH(1, false, true);
+        }
     } else {
-        if (b->tw_lds) FFTRW_LAUNCH(1, true); else FFTRW_LAUNCH(1, false);
+        if (dir < 0) {
+            if (b->tw_lds) FFTRW_LAUNCH(-1, true, false); else FFTRW_LAUNCH(-1, false, false);
+        } else {
+            if (b->tw_lds) FFTRW_LAUNCH(1, true, false); else FFTRW_LAUNCH(1, false, false);
+        }
     }
 #undef FFTRW_LAUNCH
     e = hipGetLastError();
@@ -431,6 +449,38 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
     // separate stages need no more LDS either way
     b->tw_lds = b->any_fused && tw_fits;
     b->lds = (std::max(lds, b->tw_lds ? lds_tw : (size_t)0) + 15) & ~(size_t)15;
+    // Every FFT step of a batch runs radices 2, 3, 4 and 5 only (8 and 16
+    // become 4 x 2 and 4 x 4, in place), in the fused and the separate
+    // schedules alike so that the two stay bit-identical.  When every stage is
+    // a fused unit (no LEAVE_PERMUTED, no BATCH_NO_FUSE) the batch then runs
+    // batch_kernel's LEAN form: without the separate stage kernels and the
+    // larger passes it holds four waves per SIMD instead of three (config 5:
+    // 5.95 -> 5.33 ms).
+    b->lean = !(flags & (FFTRW_FLAG_LEAVE_PERMUTED | FFTRW_FLAG_BATCH_NO_FUSE));
+    for (int i = 0; i < n; ++i) {
+        BatchItemDev &d = b->h_items[i];
+        for (int t = 0; t < d.M; ++t) {
+            FftDesc &f = d.fft[t];
+            int rad[kMaxPasses], np = 0;
+            bool fits = true;
+            for (int q = 0; q < f.npass && fits; ++q) {
+                const int r = f.radix[q];
+                const int nparts = (r == 8 || r == 16) ? 2 : 1;
+                const int parts[2] = {nparts == 2 ? 4 : r, r == 16 ? 4 : 2};
+                if (np + nparts > kMaxPasses) {
+                    fits = false;
+                    break;
+                }
+                for (int k = 0; k < nparts; ++k) rad[np++] = parts[k];
+            }
+            if (!fits) {
+                b->lean = false;  // keeps the step's own radices
+                continue;
+            }
+            f.npass = np;
+            for (int q = 0; q < np; ++q) f.radix[q] = rad[q];
+        }
+    }
     b->moved_off.resize(n);
     b->nctr = (int64_t)(sizeof(BatchCounters) / sizeof(unsigned long long));
     for (int i = 0; i < n; ++i) {
@@ -442,7 +492,10 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, b->tw_lds ? batch_kernel<-1, true> : batch_kernel<-1, false>, kThreads, b->lds);
+            &per_cu,
+            b->lean ? (b->tw_lds ? batch_kernel<-1, true, true> : batch_kernel<-1, false, true>)
+                    : (b->tw_lds ? batch_kernel<-1, true, false> : batch_kernel<-1, false, false>),
+            kThreads, b->lds);
     if (e != hipSuccess || per_cu < 1 || ncu < 1) {
         batch_free(b);
         return e != hipSuccess ? batch_fail_hip(e, "occupancy query") : fail(FFTRW_E_DEVICE, "kernel does not fit");

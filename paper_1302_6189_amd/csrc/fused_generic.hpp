@@ -172,8 +172,9 @@ __device__ __forceinline__ void store_unit_runs(C *__restrict__ out, const C *ld
 
 // Unit `unit` of a fused step: v-block unit % tiles_v of G consecutive slices.
 // TW_LDS: the twiddle table is staged in LDS (the caller checked unit_tw_fits
-// and sized the LDS block with it).
-template <typename C, int DIR, bool TW_LDS>
+// and sized the LDS block with it).  LEAN: the step's radices are 2, 3, 4 and
+// 5 only (the caller made sure), so the larger passes are not compiled in.
+template <typename C, int DIR, bool TW_LDS, bool LEAN = false>
 __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__restrict__ out, const FftDesc &f,
                                                const XposeDesc &d, int rw, int G, int64_t unit,
                                                typename RealOf<C>::type scale, bool do_scale, unsigned char *smem)
@@ -238,8 +239,12 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
         case 3: stockham_pass<3, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
         case 4: stockham_pass<4, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
         case 5: stockham_pass<5, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
-        case 8: stockham_pass<8, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
-        case 16: stockham_pass<16, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
+        case 8:
+            if constexpr (!LEAN) stockham_pass<8, DIR>(lrow, N, Ns, lanes, lane, tw, wave);
+            break;
+        case 16:
+            if constexpr (!LEAN) stockham_pass<16, DIR>(lrow, N, Ns, lanes, lane, tw, wave);
+            break;
         default: break;
         }
         Ns *= f.radix[p];
