@@ -147,8 +147,10 @@ __device__ __forceinline__ void store_block(C *__restrict__ dst, const C *lds, i
 
 // One work-group's share of a batched row FFT: rows [blk * RW, blk * RW + RW).
 // TW_LDS: the N-entry twiddle table is staged in LDS after the rows (the
-// caller sized the block for it), so the passes read it there.
-template <typename C, int DIR, bool TW_LDS = false>
+// caller sized the block for it), so the passes read it there.  LEAN: the
+// radices are 2, 3, 4 and 5 only (the caller checked), so the passes of 8 and
+// 16 are not compiled in and the kernel holds fewer registers.
+template <typename C, int DIR, bool TW_LDS = false, bool LEAN = false>
 __device__ __forceinline__ void fft_rows_block(const C *in, C *out, const FftDesc &d, int64_t blk,
                                                typename RealOf<C>::type scale, bool do_scale, C *lds)
 {
@@ -180,8 +182,12 @@ __device__ __forceinline__ void fft_rows_block(const C *in, C *out, const FftDes
         case 3: stockham_pass<3, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
         case 4: stockham_pass<4, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
         case 5: stockham_pass<5, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
-        case 8: stockham_pass<8, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
-        case 16: stockham_pass<16, DIR>(lrow, N, Ns, lanes, lane, tw, wave); break;
+        case 8:
+            if constexpr (!LEAN) stockham_pass<8, DIR>(lrow, N, Ns, lanes, lane, tw, wave);
+            break;
+        case 16:
+            if constexpr (!LEAN) stockham_pass<16, DIR>(lrow, N, Ns, lanes, lane, tw, wave);
+            break;
         default: break;
         }
         Ns *= d.radix[p];

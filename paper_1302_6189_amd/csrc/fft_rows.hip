@@ -29,12 +29,23 @@ hipError_t launch_twiddles(void *out, int64_t n, bool fp64, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename C, int DIR, bool TW_LDS>
+template <typename C, int DIR, bool TW_LDS, bool LEAN>
 __global__ void __launch_bounds__(kThreads)
     fft_rows_kernel(const C *in, C *out, FftDesc d, typename RealOf<C>::type scale, int do_scale)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    fft_rows_block<C, DIR, TW_LDS>(in, out, d, blockIdx.x, scale, do_scale != 0, reinterpret_cast<C *>(smem_raw));
+    fft_rows_block<C, DIR, TW_LDS, LEAN>(in, out, d, blockIdx.x, scale, do_scale != 0, reinterpret_cast<C *>(smem_raw));
+}
+
+// Radix lists without 8 and 16 (lengths with at most two factors 2, or the
+// lists the autotuner picks that way) run the kernels compiled for radices 2
+// to 5 only: the same passes with fewer registers (complex64 118-119 VGPRs
+// instead of 131-135, four waves per SIMD instead of three).
+bool lean_radices(const FftDesc &d)
+{
+    for (int q = 0; q < d.npass; ++q)
+        if (d.radix[q] == 8 || d.radix[q] == 16) return false;
+    return true;
 }
 
 hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in, void *out, double scale,
@@ -48,8 +59,16 @@ hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in,
     const size_t lds = ((size_t)d.rows_per_wg * d.N + (tw ? d.N : 0)) * esz;
     const int do_scale = scale != 1.0;
     dim3 grid((unsigned)nblk), block(kThreads);
-#define FFTRW_LAUNCH(C, D, T, SC) \
-    hipLaunchKernelGGL((fft_rows_kernel<C, D, T>), grid, block, lds, s, (const C *)in, (C *)out, d, SC, do_scale)
+    const bool lean = lean_radices(d);
+#define FFTRW_LAUNCH(C, D, T, SC)                                                                                  \
+    do {                                                                                                         \
+        if (lean)                                                                                                \
+            hipLaunchKernelGGL((fft_rows_kernel<C, D, T, true>), grid, block, lds, s, (const C *)in, (C *)out, d, SC, \
+                               do_scale);                                                                        \
+        else                                                                                                     \
+            hipLaunchKernelGGL((fft_rows_kernel<C, D, T, false>), grid, block, lds, s, (const C *)in, (C *)out, d, SC, \
+                               do_scale);                                                                        \
+    } while (0)
     if (fp64) {
         if (dir < 0) {
             if (tw) FFTRW_LAUNCH(double2, -1, true, scale); else FFTRW_LAUNCH(double2, -1, false, scale);
@@ -67,13 +86,13 @@ hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in,
     return hipGetLastError();
 }
 
-template <typename C, int DIR, bool TW_LDS>
+template <typename C, int DIR, bool TW_LDS, bool LEAN>
 __global__ void __launch_bounds__(kThreads)
     fft_xpose_generic_kernel(const C *in, C *out, FftDesc f, XposeDesc d, int rw, int G,
                              typename RealOf<C>::type scale, int do_scale)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    fft_xpose_unit<C, DIR, TW_LDS>(in, out, f, d, rw, G, blockIdx.x, scale, do_scale != 0, smem_raw);
+    fft_xpose_unit<C, DIR, TW_LDS, LEAN>(in, out, f, d, rw, G, blockIdx.x, scale, do_scale != 0, smem_raw);
 }
 
 // one FFT step of 2,3,5-smooth rows fused with the transpose that follows
@@ -90,9 +109,16 @@ hipError_t launch_fft_xpose_generic(const FftDesc &f, const XposeDesc &d, bool f
     const size_t lds = fused_unit_bytes(f.N, rw, G, esz, tw);
     const int do_scale = scale != 1.0;
     dim3 grid((unsigned)nblk), block(kThreads);
+    const bool lean = lean_radices(f);
 #define FFTRW_LAUNCH(C, D, T, SC)                                                                             \
-    hipLaunchKernelGGL((fft_xpose_generic_kernel<C, D, T>), grid, block, lds, s, (const C *)in, (C *)out, f, d, \
-                       rw, G, SC, do_scale)
+    do {                                                                                                    \
+        if (lean)                                                                                           \
+            hipLaunchKernelGGL((fft_xpose_generic_kernel<C, D, T, true>), grid, block, lds, s, (const C *)in, \
+                               (C *)out, f, d, rw, G, SC, do_scale);                                        \
+        else                                                                                                \
+            hipLaunchKernelGGL((fft_xpose_generic_kernel<C, D, T, false>), grid, block, lds, s, (const C *)in, \
+                               (C *)out, f, d, rw, G, SC, do_scale);                                        \
+    } while (0)
     if (fp64) {
         if (dir < 0) {
             if (tw) FFTRW_LAUNCH(double2, -1, true, scale); else FFTRW_LAUNCH(double2, -1, false, scale);
