@@ -533,9 +533,9 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
     b->tuned = tuned;
     int64_t units = 0;
     for (int64_t u : b->level_units) units += u;
-    log_line(1, "batch of %d items: %lld units in %zu stage levels, %d resident groups, %s stages%s", n,
+    log_line(1, "batch of %d items: %lld units in %zu stage levels, %d resident groups, %s stages%s%s", n,
              (long long)units, b->level_units.size(), b->grid, b->any_fused ? "fused" : "separate",
-             tuned ? ", tuned" : "");
+             b->lean ? " (lean kernel: fused units of radices 2..5)" : "", tuned ? ", tuned" : "");
     *out = b;
     return FFTRW_OK;
 }
