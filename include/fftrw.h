@@ -153,8 +153,9 @@ int fft_comm_volume(int M, const int64_t *dims, int64_t P, const int8_t *order,
  * processes, each sending every point of the row once, so the row adds
  * N * ceil(log2 c) points.  With it the 64^3 comparison of Section 4 against
  * the 3-D method (Eq. (23)) peaks at 8,192 processes at 11.6 times.  This
- * reading was chosen because it reproduces that printed 11.6: it is fitted
- * to the one number it is checked against, so its parity is unpinned.
+ * reading was chosen because it reproduces that printed 11.6 (the paper's
+ * own algorithm for a split row is unknown); given the reading, the count is
+ * the number of points an executed binary-exchange FFT sends.
  *   per_step[M] (nullable): one count per FFT step t = 1..M (0 below level M).
  *   total: their sum.
  * Errors: FFTRW_E_ARG, FFTRW_E_SIZE, FFTRW_E_ORDER, FFTRW_E_ROWSPLIT if P > T.

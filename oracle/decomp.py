@@ -191,9 +191,11 @@ def split_row_volume(dims, P: int, perm) -> int:
     processes runs ceil(log2 c) butterfly stages across processes, each
     sending all N points of the row.  0 below level M.
 
-    Parity unpinned: this reading was chosen because it reproduces the 11.6
-    printed for the 64^3 comparison with the 3-D method in Section 4, so that
-    check confirms the choice rather than the function."""
+    The reading was chosen because it reproduces the 11.6 printed for the
+    64^3 comparison with the 3-D method in Section 4, so that check confirms
+    the choice rather than the paper's intent.  Given the reading, the count
+    is pinned against the points an executed binary exchange sends
+    (rowsplit.binary_exchange_row, whose result is checked against the DFT)."""
     pdims = [int(dims[a]) for a in perm]
     M = len(pdims)
     if level(pdims, P) < M:
