@@ -297,6 +297,8 @@ def main():
                     help="also time the staged pack -> exchange -> unpack transposes")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="one forward transform plus a plain 1 GiB device copy, for counter runs")
+    ap.add_argument("--batch-probe", action="store_true",
+                    help="the 256-item batched form: one warm-up and one counted launch, for counter runs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -309,6 +311,22 @@ def main():
     import torch
 
     from paper_1302_6189_amd import fftrw, inputs
+
+    if args.batch_probe:
+        # counters are read per dispatch: the batched form's persistent kernel
+        # (built-in radix lists, no autotuner), launched twice
+        items = inputs.batch_items(256, seed=5)
+        xs = [torch.from_numpy(inputs.uniform(d, 1000 + i, np.complex64)).cuda() for i, (d, _) in enumerate(items)]
+        ys = [torch.empty_like(v) for v in xs]
+        batch = fftrw.Batch(items, flags=fftrw.FLAG_COUNT_MOVED)
+        for _ in range(2):
+            batch.exec_fwd(xs, ys, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        st = batch.stats()
+        batch.destroy()
+        print(json.dumps({"batch_probe": "done", "units": st["units"], "timeouts": st["error"],
+                          "counts_match": st["moved"] == st["analytic"]}), flush=True)
+        return
 
     dims = (512, 512, 512)
     T = math.prod(dims)
