@@ -77,9 +77,15 @@ constexpr int kLevelTasksLds = 256;
 // real-time clock ticks (100 MHz) a work-group may wait at one barrier
 constexpr unsigned long long kWaitTicks = 200000000ull;
 
+// The buffer of a stage, as a work-group-uniform value: the compiler then
+// waits for the descriptor's pointer once, where it is read, instead of
+// before each of the unit's row loads that use it.
 __device__ __forceinline__ float2 *batch_buf(const BatchItemDev &it, int kind)
 {
-    return kind == 0 ? const_cast<float2 *>(it.in) : (kind == 1 ? it.out : it.work);
+    const uint64_t p = (uint64_t)(kind == 0 ? const_cast<float2 *>(it.in) : (kind == 1 ? it.out : it.work));
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+    return reinterpret_cast<float2 *>(((uint64_t)hi << 32) | lo);
 }
 
 // The inverse (whose last stage also scales) is held to three waves per SIMD

@@ -18,6 +18,36 @@ template <typename C> struct RealOf;
 template <> struct RealOf<float2> { using type = float; };
 template <> struct RealOf<double2> { using type = double; };
 
+// Pointers that a kernel reads out of a descriptor in memory are generic
+// (flat) pointers to the compiler, and flat accesses count on the LDS wait
+// counter as well: a wait for one LDS read then also waits for every flat
+// load and store still in flight, which serialises a thread's HBM accesses.
+// Passing such a pointer through the global address space lets the compiler
+// issue global_ loads and stores, whose waits are separate from the LDS's.
+template <typename T> __device__ __forceinline__ T *as_global(T *p)
+{
+    return (T *)(__attribute__((address_space(1))) T *)p;
+}
+
+// HBM accesses through the global address space.  A pointer a kernel reads
+// out of a descriptor in memory is a generic (flat) pointer to the compiler,
+// and flat accesses count on the LDS wait counter too: a wait for one LDS
+// read then also waits for every flat load and store still in flight, which
+// serialises a thread's HBM accesses.  Global loads and stores have waits of
+// their own.  Only for pointers into device memory (never LDS).
+template <typename T> __device__ __forceinline__ T gld_nt(const T *p)
+{
+    return __builtin_nontemporal_load((const __attribute__((address_space(1))) T *)p);
+}
+template <typename T> __device__ __forceinline__ void gst_nt(T v, T *p)
+{
+    __builtin_nontemporal_store(v, (__attribute__((address_space(1))) T *)p);
+}
+template <typename T> __device__ __forceinline__ T gld(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
 template <typename C> __device__ __forceinline__ C mk(typename RealOf<C>::type x, typename RealOf<C>::type y)
 {
     C r;

@@ -37,6 +37,7 @@ __host__ __device__ inline int unit_pitch(int N, size_t esz) { return esz == 8 &
 // and every row keeps at least one lane of the 256-thread group.
 inline void fused_unit_shape(int N, size_t esz, int64_t Nv, int64_t nslices, int budget, int *rw, int *G)
 {
+    budget = budget < kUnitItems * kThreads ? budget : kUnitItems * kThreads;  // one load pass per unit
     const int P = unit_pitch(N, esz);
     int r = 1;
     while (r * 2 <= 256 && (int64_t)r * 2 * P <= budget && r * 2 <= 2 * Nv - 1) r *= 2;
@@ -63,12 +64,14 @@ __host__ __device__ inline size_t fused_unit_bytes(int N, int rw, int G, size_t 
 // Rows (slice g0 + gi, v0 + r) of a unit into LDS (row rho = gi rw + r at
 // rho S), W consecutive values per access (W = 2: 16-byte loads and LDS
 // stores of complex64, N and S even, so every row starts on an even element
-// in HBM and 16 bytes aligned in LDS).  Group e = rho N / W + c
-// is stepped by kThreads without divisions; up to kUnitItems values are in
-// flight per thread before any is stored to LDS (a unit holds at most 16
-// values per thread).  The owner changes of the unit's rows are counted
-// while the first loads are in flight: every thread with rows to count
-// (threadIdx.x < ng nv) has loads too.
+// in HBM and 16 bytes aligned in LDS).  Group e = rho N / W + c is stepped by
+// kThreads without divisions.  A unit holds at most kUnitItems values per
+// thread (fused_unit_shape keeps it within kUnitItems * kThreads values), so
+// every load of the thread is issued before any is stored to LDS, in one
+// pass with no loop around it: a loop would make the compiler wait for the
+// loads of one trip before it reuses their registers on the next.  The owner
+// changes of the unit's rows are counted while the loads are in flight:
+// every thread with rows to count (threadIdx.x < ng nv) has loads too.
 template <int W, typename C>
 __device__ __forceinline__ void load_unit_rows(const C *__restrict__ in, C *lds, const FftDesc &f,
                                                const XposeDesc &d, const int64_t *abase, int S, int rw, int nv,
@@ -81,51 +84,47 @@ __device__ __forceinline__ void load_unit_rows(const C *__restrict__ in, C *lds,
     int rho = threadIdx.x / NW, c = threadIdx.x - rho * NW;
     int gi = rho / nv, r = rho - gi * nv;
     const int drg = drho / nv, drr = drho - drg * nv;
-    bool counted = false;
-    while (gi < ng) {
-        C val[ITEMS][W];
-        int at[ITEMS];
+    C val[ITEMS][W];
+    int at[ITEMS];
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            at[j] = -1;
-            if (gi < ng) {
-                at[j] = (gi * rw + r) * S + c * W;
-                const C *p = in + abase[gi] + (v0 + r) * d.a_sv + c * W;
-                if constexpr (W == 2) {
-                    const xf4 w = __builtin_nontemporal_load(reinterpret_cast<const xf4 *>(p));
-                    val[j][0] = mk<C>(w.x, w.y);
-                    val[j][1] = mk<C>(w.z, w.w);
-                } else {
-                    val[j][0] = xld(p);
-                }
-                c += dc;
-                gi += drg;
-                r += drr;
-                if (c >= NW) {
-                    c -= NW;
-                    ++r;
-                }
-                while (r >= nv) {
-                    r -= nv;
-                    ++gi;
-                }
+    for (int j = 0; j < ITEMS; ++j) {
+        at[j] = -1;
+        if (gi < ng) {
+            at[j] = (gi * rw + r) * S + c * W;
+            const C *p = in + abase[gi] + (v0 + r) * d.a_sv + c * W;
+            if constexpr (W == 2) {
+                const xf4 w = gld_nt(reinterpret_cast<const xf4 *>(p));
+                val[j][0] = mk<C>(w.x, w.y);
+                val[j][1] = mk<C>(w.z, w.w);
+            } else {
+                val[j][0] = xld(p);
+            }
+            // c < NW and r < nv before the step, dc < NW and drr < nv: each
+            // wraps at most once
+            c += dc;
+            gi += drg;
+            r += drr;
+            if (c >= NW) {
+                c -= NW;
+                ++r;
+            }
+            if (r >= nv) {
+                r -= nv;
+                ++gi;
             }
         }
-        if (d.count && !counted) {
-            moved = tile_moved(d, g0, ng, 0, N, v0, nv);
-            counted = true;
-        }
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j)
-            if (at[j] >= 0) {
-                if constexpr (W == 2) {
-                    const xf4 w4 = {val[j][0].x, val[j][0].y, val[j][1].x, val[j][1].y};
-                    *reinterpret_cast<xf4 *>(lds + at[j]) = w4;
-                } else {
-                    lds[at[j]] = val[j][0];
-                }
-            }
     }
+    if (d.count) moved = tile_moved(d, g0, ng, 0, N, v0, nv);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+        if (at[j] >= 0) {
+            if constexpr (W == 2) {
+                const xf4 w4 = {val[j][0].x, val[j][0].y, val[j][1].x, val[j][1].y};
+                *reinterpret_cast<xf4 *>(lds + at[j]) = w4;
+            } else {
+                lds[at[j]] = val[j][0];
+            }
+        }
 }
 
 // The transformed rows to B: frequency k of row (gi, r) at (slice g0 + gi,
@@ -152,7 +151,7 @@ __device__ __forceinline__ void store_unit_runs(C *__restrict__ out, const C *ld
         C *p = out + bbase[gi] + (int64_t)k * d.b_su + v0 + r * W;
         if constexpr (W == 2) {
             const xf4 w = {q[0].x, q[0].y, q[1].x, q[1].y};
-            __builtin_nontemporal_store(w, reinterpret_cast<xf4 *>(p));
+            gst_nt(w, reinterpret_cast<xf4 *>(p));
         } else {
             xst(p, q[0]);
         }

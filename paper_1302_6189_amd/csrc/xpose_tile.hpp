@@ -39,10 +39,10 @@ typedef double xd2 __attribute__((ext_vector_type(2)));
 template <typename C> __device__ __forceinline__ C xld(const C *p)
 {
     if constexpr (sizeof(C) == 8) {
-        xf2 w = __builtin_nontemporal_load(reinterpret_cast<const xf2 *>(p));
+        xf2 w = gld_nt(reinterpret_cast<const xf2 *>(p));
         return mk<C>(w.x, w.y);
     } else {
-        xd2 w = __builtin_nontemporal_load(reinterpret_cast<const xd2 *>(p));
+        xd2 w = gld_nt(reinterpret_cast<const xd2 *>(p));
         return mk<C>(w.x, w.y);
     }
 }
@@ -50,10 +50,10 @@ template <typename C> __device__ __forceinline__ void xst(C *p, C v)
 {
     if constexpr (sizeof(C) == 8) {
         xf2 w = {v.x, v.y};
-        __builtin_nontemporal_store(w, reinterpret_cast<xf2 *>(p));
+        gst_nt(w, reinterpret_cast<xf2 *>(p));
     } else {
         xd2 w = {v.x, v.y};
-        __builtin_nontemporal_store(w, reinterpret_cast<xd2 *>(p));
+        gst_nt(w, reinterpret_cast<xd2 *>(p));
     }
 }
 
@@ -215,7 +215,7 @@ __device__ __forceinline__ void xpose_tile(const C *__restrict__ in, C *__restri
                 const C *p = in + abase + (v0 + iv) * d.a_sv + u0 + iu;
                 C *trow = tile + (g * TV + iv) * ldt + iu;
                 if constexpr (VU == 2) {
-                    xf4 w = __builtin_nontemporal_load(reinterpret_cast<const xf4 *>(p));
+                    xf4 w = gld_nt(reinterpret_cast<const xf4 *>(p));
                     trow[0] = mk<C>(w.x, w.y);
                     trow[1] = mk<C>(w.z, w.w);
                 } else {
@@ -251,7 +251,7 @@ __device__ __forceinline__ void xpose_tile(const C *__restrict__ in, C *__restri
                 if constexpr (VV == 2) {
                     const C a0 = tcol[0], a1 = tcol[ldt];
                     xf4 w = {a0.x, a0.y, a1.x, a1.y};
-                    __builtin_nontemporal_store(w, reinterpret_cast<xf4 *>(p));
+                    gst_nt(w, reinterpret_cast<xf4 *>(p));
                 } else {
                     xst(p, tcol[0]);
                 }
