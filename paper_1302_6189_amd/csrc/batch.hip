@@ -42,9 +42,7 @@ namespace fftrw {
 constexpr int kMaxStages = 2 * kMaxDims;
 
 struct BatchItemDev {
-    const float2 *in;
-    float2 *out;
-    float2 *work;
+    float2 *buf[3];                 // 0 in (read only), 1 out, 2 work
     int M;
     int nstage;                     // 2M (2M - 1 with LEAVE_PERMUTED); fused: M
     int fused;                      // stage t = FFT step t fused with transpose t
@@ -77,15 +75,24 @@ constexpr int kLevelTasksLds = 256;
 // real-time clock ticks (100 MHz) a work-group may wait at one barrier
 constexpr unsigned long long kWaitTicks = 200000000ull;
 
-// The buffer of a stage, as a work-group-uniform value: the compiler then
-// waits for the descriptor's pointer once, where it is read, instead of
-// before each of the unit's row loads that use it.
+// Takes the next unit index from a level's claim counter (a 64-bit word
+// whose low half counts; levels hold fewer than 2^32 units).  A wrapping
+// increment rather than an add: the compiler rewrites a single lane's atomic
+// add into a wave-wide scan that needs the result at once, which would wait
+// for every load and store the wave has in flight; the increment's result is
+// waited for only where it is used.
+__device__ __forceinline__ unsigned long long claim(unsigned long long *ctr)
+{
+    return __builtin_amdgcn_atomic_inc32(reinterpret_cast<unsigned *>(ctr), 0xffffffffu, __ATOMIC_RELAXED, "agent");
+}
+
+// The buffer of a stage.  One uniform address, read through the scalar
+// cache: a vector load would count on the wait counter that the unit's HBM
+// stores also count on, and waiting for it would wait for the previous
+// unit's stores as well.
 __device__ __forceinline__ float2 *batch_buf(const BatchItemDev &it, int kind)
 {
-    const uint64_t p = (uint64_t)(kind == 0 ? const_cast<float2 *>(it.in) : (kind == 1 ? it.out : it.work));
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
-    return reinterpret_cast<float2 *>(((uint64_t)hi << 32) | lo);
+    return it.buf[__builtin_amdgcn_readfirstlane(kind)];
 }
 
 // The inverse (whose last stage also scales) is held to three waves per SIMD
@@ -112,18 +119,19 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(L
         if (in_lds)
             for (int i = threadIdx.x; i < t1 - t0; i += kThreads) s_unit0[i] = tasks[t0 + i].unit0;
         __syncthreads();
-        // thread 0 claims units from the level's counter -- the next claim is
-        // issued before the current unit runs, hiding its latency -- finds the
-        // unit's task and hands both to the work-group
+        // Thread 0 claims units from the level's counter and finds each one's
+        // task (a binary search over the level's task starts).  A unit's
+        // successor is claimed when the unit starts and handed to the
+        // work-group (s_unit, s_task) in the middle of the unit, once the
+        // unit's own row loads have arrived: loads, stores and atomics count
+        // on one wait counter in issue order, so reading the claim at the
+        // next unit's start would also wait for this unit's stores.
         unsigned long long next = 0, ndone = 0;
-        if (threadIdx.x == 0) next = atomicAdd(&ctr->next[lv], 1ull);
-        for (;;) {
+        auto publish = [&]() {
             if (threadIdx.x == 0) {
                 const int64_t u = (int64_t)next;
                 int lo = 0;
                 if (u < nunits) {
-                    ++ndone;
-                    next = atomicAdd(&ctr->next[lv], 1ull);
                     int hi = t1 - t0 - 1;
                     while (lo < hi) {
                         const int mid = (lo + hi + 1) >> 1;
@@ -136,11 +144,21 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(L
                 s_unit = u;
                 s_task = t0 + lo;
             }
-            __syncthreads();
+        };
+        if (threadIdx.x == 0) next = claim(&ctr->next[lv]);
+        publish();
+        __syncthreads();
+        for (;;) {
+            // every unit function synchronises the work-group before it calls
+            // publish (and non-fused units are preceded by a barrier), so these
+            // reads are done before thread 0 overwrites the values
             const int64_t u = s_unit;
             const int lo = s_task;
-            __syncthreads();  // every thread has read them before they change
             if (u >= nunits) break;
+            if (threadIdx.x == 0) {
+                ++ndone;
+                next = claim(&ctr->next[lv]);
+            }
             const BatchTask tk = tasks[lo];
             const BatchItemDev &it = items[tk.item];
             const int64_t local = u - tk.unit0;
@@ -150,18 +168,24 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(L
             if constexpr (LEAN) {
                 const bool last = st == it.M - 1;
                 fft_xpose_unit<float2, DIR, TW_LDS, true>(src, dst, it.fft[st], it.xp[st], it.frw[st], it.fg[st], local,
-                                                          DIR > 0 && last ? it.inv_scale : 1.f, DIR > 0 && last, smem);
+                                                          DIR > 0 && last ? it.inv_scale : 1.f, DIR > 0 && last, smem,
+                                                          publish);
                 continue;
             }
+            if (it.fused && st < it.nx) {
+                const bool last = st == it.M - 1;
+                fft_xpose_unit<float2, DIR, TW_LDS>(src, dst, it.fft[st], it.xp[st], it.frw[st], it.fg[st], local,
+                                                    DIR > 0 && last ? it.inv_scale : 1.f, DIR > 0 && last, smem,
+                                                    publish);
+                continue;
+            }
+            // the other unit kinds take the next unit before they start
+            __syncthreads();
+            publish();
             if (it.fused) {
                 const bool last = st == it.M - 1;
-                const float sc = DIR > 0 && last ? it.inv_scale : 1.f;
-                if (st < it.nx)
-                    fft_xpose_unit<float2, DIR, TW_LDS>(src, dst, it.fft[st], it.xp[st], it.frw[st], it.fg[st], local,
-                                                sc, DIR > 0 && last, smem);
-                else
-                    fft_rows_block<float2, DIR>(src, dst, it.fft[st], local, sc, DIR > 0 && last,
-                                                reinterpret_cast<float2 *>(smem));
+                fft_rows_block<float2, DIR>(src, dst, it.fft[st], local, DIR > 0 && last ? it.inv_scale : 1.f,
+                                            DIR > 0 && last, reinterpret_cast<float2 *>(smem));
                 continue;
             }
             const int t = st >> 1;
@@ -350,7 +374,7 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
         d.M = it.M;
         const int nx = leave ? it.M - 1 : it.M;
         d.nx = nx;
-        d.work = (float2 *)p->work;
+        d.buf[2] = (float2 *)p->work;
         d.inv_scale = (float)(1.0 / (double)p->T);
         int64_t units = 0;
         // fused schedule: one unit = RW rows consecutive in v of one slice, the
@@ -446,6 +470,12 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
             if (cnt <= 0) continue;
             b->h_tasks.push_back({i, s, lvl, cnt});
             lvl += cnt;
+        }
+        // claims count in 32 bits (see claim); every group claims at most
+        // once past the end of a level
+        if (lvl >= (int64_t{1} << 31)) {
+            batch_free(b);
+            return fail(FFTRW_E_SIZE, "a stage level of the batch has 2^31 or more units");
         }
         b->level_units.push_back(lvl);
         b->total += lvl;
@@ -559,9 +589,9 @@ static int batch_exec(fft_batch_t b, void *const *in, void *const *out, void *st
             return fail(FFTRW_E_ARG, "item " + std::to_string(i) +
                                          ": fused stages need in != out (plan with FFTRW_FLAG_BATCH_NO_FUSE for in place)");
         BatchItemDev &d = b->h_items[i];
-        if (d.in != in[i] || d.out != out[i]) changed = true;
-        d.in = (const float2 *)in[i];
-        d.out = (float2 *)out[i];
+        if (d.buf[0] != in[i] || d.buf[1] != out[i]) changed = true;
+        d.buf[0] = (float2 *)in[i];
+        d.buf[1] = (float2 *)out[i];
     }
     hipStream_t s = (hipStream_t)stream;
     if (changed) {

@@ -43,9 +43,24 @@ template <typename T> __device__ __forceinline__ void gst_nt(T v, T *p)
 {
     __builtin_nontemporal_store(v, (__attribute__((address_space(1))) T *)p);
 }
+// one complex value (float2 or double2), cached
 template <typename T> __device__ __forceinline__ T gld(const T *p)
 {
-    return *(const __attribute__((address_space(1))) T *)p;
+    if constexpr (sizeof(T) == 8) {
+        typedef float v2 __attribute__((ext_vector_type(2)));
+        const v2 w = *(const __attribute__((address_space(1))) v2 *)p;
+        T r;
+        r.x = w.x;
+        r.y = w.y;
+        return r;
+    } else {
+        typedef double v2 __attribute__((ext_vector_type(2)));
+        const v2 w = *(const __attribute__((address_space(1))) v2 *)p;
+        T r;
+        r.x = w.x;
+        r.y = w.y;
+        return r;
+    }
 }
 
 template <typename C> __device__ __forceinline__ C mk(typename RealOf<C>::type x, typename RealOf<C>::type y)

@@ -169,14 +169,22 @@ __device__ __forceinline__ void store_unit_runs(C *__restrict__ out, const C *ld
     }
 }
 
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
 // Unit `unit` of a fused step: v-block unit % tiles_v of G consecutive slices.
 // TW_LDS: the twiddle table is staged in LDS (the caller checked unit_tw_fits
 // and sized the LDS block with it).  LEAN: the step's radices are 2, 3, 4 and
 // 5 only (the caller made sure), so the larger passes are not compiled in.
-template <typename C, int DIR, bool TW_LDS, bool LEAN = false>
+// hook() runs once the unit's rows are in LDS, after a barrier that every
+// thread passed after entering the unit; no HBM access of the unit's is in
+// flight then except the owner-count atomics.
+template <typename C, int DIR, bool TW_LDS, bool LEAN = false, typename Hook = NoHook>
 __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__restrict__ out, const FftDesc &f,
                                                const XposeDesc &d, int rw, int G, int64_t unit,
-                                               typename RealOf<C>::type scale, bool do_scale, unsigned char *smem)
+                                               typename RealOf<C>::type scale, bool do_scale, unsigned char *smem,
+                                               Hook hook = Hook())
 {
     const int N = f.N;
     const int S = unit_pitch(N, sizeof(C));
@@ -198,6 +206,12 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
     }
     __syncthreads();
 
+    // a staged twiddle table's first kThreads entries are loaded before the
+    // rows, so that both arrive in one memory round trip
+    const C *gtw = reinterpret_cast<const C *>(f.tw);
+    C tw0 = mk<C>(0, 0);
+    if constexpr (TW_LDS)
+        if (threadIdx.x < N) tw0 = gld(gtw + threadIdx.x);
     // rows (slice g0 + gi, v0 + r), rho = gi nv + r: N contiguous values each,
     // read in 16-byte pairs when N is even (complex64)
     int moved = 0;
@@ -210,9 +224,10 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
     } else {
         load_unit_rows<1>(in, lds, f, d, abase, S, rw, nv, ng, g0, v0, moved);
     }
+    hook();
     if constexpr (TW_LDS) {
-        const C *gtw = reinterpret_cast<const C *>(f.tw);
-        for (int i = threadIdx.x; i < N; i += kThreads) ltw[i] = gtw[i];
+        if (threadIdx.x < N) ltw[threadIdx.x] = tw0;
+        for (int i = threadIdx.x + kThreads; i < N; i += kThreads) ltw[i] = gld(gtw + i);
     }
     if (d.count) {
         // each wave publishes its sum at once: work left for the end of the
