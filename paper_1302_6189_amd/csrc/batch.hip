@@ -72,6 +72,10 @@ struct BatchCounters {
 // task starts of one level held in LDS for the per-unit search
 constexpr int kLevelTasksLds = 256;
 
+// s_waitcnt operand: vector memory count 0 (bits 3:0 and 15:14), the export
+// and LDS/scalar counts at their maxima (bits 6:4 and 11:8)
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 // real-time clock ticks (100 MHz) a work-group may wait at one barrier
 constexpr unsigned long long kWaitTicks = 200000000ull;
 
@@ -203,10 +207,18 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(L
             }
         }
         if (lv + 1 == nlevels) break;
-        // level barrier: publish the units this group completed, wait for all
-        __threadfence();  // release this work-group's writes of the level
+        // Level barrier: publish the units this group completed, wait for
+        // all.  Every wave first waits until its own stores have completed
+        // (they are then in the L2; a workgroup-scope release does not wait
+        // for them); the agent-scope fences are issued by thread 0's wave
+        // alone: its release writes back the L2 (whatever wave wrote the
+        // lines) before the count is published, and its acquire invalidates
+        // the L2 and this CU's L1, which the group's other waves read
+        // through after the second barrier.
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         __syncthreads();
         if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const unsigned long long target = (unsigned long long)nunits;
             if (ndone) atomicAdd(&ctr->done[lv], ndone);
             const unsigned long long w0 = wall_clock64();
@@ -217,9 +229,9 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(L
                 }
                 __builtin_amdgcn_s_sleep(10);
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
-        __threadfence();  // acquire the other work-groups' writes
     }
 }
 
