@@ -76,6 +76,11 @@ constexpr int kLevelTasksLds = 256;
 // and LDS/scalar counts at their maxima (bits 6:4 and 11:8)
 constexpr int kWaitVmcnt0 = 0x0F70;
 
+// units per claim of the level counter, and the level's last units claimed
+// one at a time (this many per work-group of the grid)
+constexpr int kClaimUnits = 4;
+constexpr int kClaimTail = 2;
+
 // real-time clock ticks (100 MHz) a work-group may wait at one barrier
 constexpr unsigned long long kWaitTicks = 200000000ull;
 
@@ -85,7 +90,7 @@ constexpr unsigned long long kWaitTicks = 200000000ull;
 // add into a wave-wide scan that needs the result at once, which would wait
 // for every load and store the wave has in flight; the increment's result is
 // waited for only where it is used.
-__device__ __forceinline__ unsigned long long claim(unsigned long long *ctr)
+__device__ __forceinline__ unsigned claim(unsigned long long *ctr)
 {
     return __builtin_amdgcn_atomic_inc32(reinterpret_cast<unsigned *>(ctr), 0xffffffffu, __ATOMIC_RELAXED, "agent");
 }
@@ -103,8 +108,9 @@ __device__ __forceinline__ float2 *batch_buf(const BatchItemDev &it, int kind)
 // (at most 168 VGPRs; it needs one more otherwise, which would leave two).
 // The forward fits without the hint and runs 1% faster without it.
 // LEAN: every stage of every item is a fused unit with radices 2, 3, 4 and 5
-// only; without the other stage kernels and the larger passes the kernel
-// fits four waves per SIMD.
+// only, and every item's buffers hold fewer than 2^32 bytes (32-bit offsets);
+// without the other stage kernels and the larger passes the kernel fits four
+// waves per SIMD.
 template <int DIR, bool TW_LDS, bool LEAN>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LEAN ? 4 : (DIR > 0 ? 3 : 1))))
     batch_kernel(const BatchItemDev *__restrict__ items, const BatchTask *__restrict__ tasks,
@@ -114,7 +120,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(L
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t s_unit0[kLevelTasksLds];
     __shared__ int64_t s_unit;
-    __shared__ int s_task;
+    __shared__ int s_task, s_end;
     for (int lv = 0; lv < nlevels; ++lv) {
         const int64_t nunits = level_units[lv];
         const int t0 = level_task0[lv], t1 = level_task0[lv + 1];
@@ -124,33 +130,62 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(L
             for (int i = threadIdx.x; i < t1 - t0; i += kThreads) s_unit0[i] = tasks[t0 + i].unit0;
         __syncthreads();
         // Thread 0 claims units from the level's counter and finds each one's
-        // task (a binary search over the level's task starts).  A unit's
-        // successor is claimed when the unit starts and handed to the
+        // task (a binary search over the level's task starts, skipped while
+        // the units stay in one task).  A claim takes a chunk of kClaimUnits
+        // consecutive units, and single units for the level's last
+        // kClaimTail x grid, so that few atomics reach the one counter and
+        // the level still ends evenly.  A unit's successor is handed to the
         // work-group (s_unit, s_task) in the middle of the unit, once the
-        // unit's own row loads have arrived: loads, stores and atomics count
-        // on one wait counter in issue order, so reading the claim at the
-        // next unit's start would also wait for this unit's stores.
-        unsigned long long next = 0, ndone = 0;
+        // unit's own row loads have arrived, and a new chunk is claimed when
+        // the last unit of the current one starts: loads, stores and atomics
+        // count on one wait counter in issue order, so reading a claim at
+        // the next unit's start would also wait for this unit's stores.
+        // (a level has fewer than 2^31 units, and claims stop one chunk past
+        // its end per work-group, so unit numbers fit in 32 bits)
+        const int nu32 = (int)nunits;
+        const int tail = min(nu32, (int)gridDim.x * kClaimTail);
+        const int nchunk = (nu32 - tail) / kClaimUnits;  // chunks of kClaimUnits
+        const int head = nchunk * kClaimUnits;
+        // Thread 0 keeps the unit being run and its task in s_unit and s_task
+        // (which the work-group reads), the end of its chunk in s_end, and
+        // the claim in flight in a register.
+        unsigned pending = 0, ndone = 0;
+        // thread 0: publish unit `cur` of chunk end `end`, its task searched
+        // from task index `task` (counted from t0) on
+        auto publish_unit = [&](int cur, int end, int task) {
+            const int last = t1 - t0 - 1;
+            if (cur < nu32 && task < last &&
+                cur >= (in_lds ? s_unit0[task + 1] : tasks[t0 + task + 1].unit0)) {
+                int lo = task + 1, hi = last;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if ((in_lds ? s_unit0[mid] : tasks[t0 + mid].unit0) <= cur)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                task = lo;
+            }
+            s_unit = cur;
+            s_end = end;
+            s_task = t0 + task;
+        };
+        // thread 0: the first unit of claimed chunk c
+        auto publish_chunk = [&](unsigned c, int task) {
+            const int ci = (int)min(c, (unsigned)nu32);  // past the end: a unit >= nunits
+            const int cur = ci < nchunk ? ci * kClaimUnits : min(head + (ci - nchunk), nu32);
+            publish_unit(cur, ci < nchunk ? cur + kClaimUnits : cur + 1, task);
+        };
         auto publish = [&]() {
             if (threadIdx.x == 0) {
-                const int64_t u = (int64_t)next;
-                int lo = 0;
-                if (u < nunits) {
-                    int hi = t1 - t0 - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if ((in_lds ? s_unit0[mid] : tasks[t0 + mid].unit0) <= u)
-                            lo = mid;
-                        else
-                            hi = mid - 1;
-                    }
-                }
-                s_unit = u;
-                s_task = t0 + lo;
+                const int cur = (int)s_unit, end = s_end, task = s_task - t0;
+                if (cur + 1 < end)
+                    publish_unit(cur + 1, end, task);
+                else
+                    publish_chunk(pending, task);
             }
         };
-        if (threadIdx.x == 0) next = claim(&ctr->next[lv]);
-        publish();
+        if (threadIdx.x == 0) publish_chunk(claim(&ctr->next[lv]), 0);
         __syncthreads();
         for (;;) {
             // every unit function synchronises the work-group before it calls
@@ -161,7 +196,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(L
             if (u >= nunits) break;
             if (threadIdx.x == 0) {
                 ++ndone;
-                next = claim(&ctr->next[lv]);
+                if (u + 1 >= s_end) pending = claim(&ctr->next[lv]);
             }
             const BatchTask tk = tasks[lo];
             const BatchItemDev &it = items[tk.item];
@@ -171,9 +206,10 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(L
             float2 *dst = batch_buf(it, it.dst[st]);
             if constexpr (LEAN) {
                 const bool last = st == it.M - 1;
-                fft_xpose_unit<float2, DIR, TW_LDS, true>(src, dst, it.fft[st], it.xp[st], it.frw[st], it.fg[st], local,
-                                                          DIR > 0 && last ? it.inv_scale : 1.f, DIR > 0 && last, smem,
-                                                          publish);
+                fft_xpose_unit<float2, DIR, TW_LDS, true, true>(src, dst, it.fft[st], it.xp[st], it.frw[st], it.fg[st],
+                                                                local,
+                                                                DIR > 0 && last ? it.inv_scale : 1.f, DIR > 0 && last,
+                                                                smem, publish);
                 continue;
             }
             if (it.fused && st < it.nx) {
@@ -220,7 +256,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(L
         if (threadIdx.x == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const unsigned long long target = (unsigned long long)nunits;
-            if (ndone) atomicAdd(&ctr->done[lv], ndone);
+            if (ndone) atomicAdd(&ctr->done[lv], (unsigned long long)ndone);
             const unsigned long long w0 = wall_clock64();
             while (__hip_atomic_load(&ctr->done[lv], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 if (wall_clock64() - w0 > wait_ticks) {
@@ -505,6 +541,8 @@ int fft_batch_plan(fft_batch_t *out, int n, const fft_item_desc *items, int prec
     // larger passes it holds four waves per SIMD instead of three (config 5:
     // 5.95 -> 5.33 ms).
     b->lean = !(flags & (FFTRW_FLAG_LEAVE_PERMUTED | FFTRW_FLAG_BATCH_NO_FUSE));
+    for (fft_plan_t p : b->plans)
+        if (p->T * (int64_t)sizeof(float2) >= (int64_t{1} << 32)) b->lean = false;  // 32-bit offsets
     for (int i = 0; i < n; ++i) {
         BatchItemDev &d = b->h_items[i];
         for (int t = 0; t < d.M; ++t) {

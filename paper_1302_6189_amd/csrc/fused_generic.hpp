@@ -61,6 +61,18 @@ __host__ __device__ inline size_t fused_unit_bytes(int N, int rw, int G, size_t 
            (tw_lds ? (((size_t)N * esz + 15) & ~(size_t)15) : 0) + (size_t)G * 16 + 16;
 }
 
+// Element `off` of an array of fewer than 2^32 bytes: the byte offset is
+// formed in 32 bits and added to the (uniform) base, so the access takes the
+// scalar-base, 32-bit-offset form instead of 64-bit address arithmetic.
+template <typename C> __device__ __forceinline__ C *at_off32(C *base, uint32_t off)
+{
+    return reinterpret_cast<C *>(reinterpret_cast<char *>(base) + off * (uint32_t)sizeof(C));
+}
+template <typename C> __device__ __forceinline__ const C *at_off32(const C *base, uint32_t off)
+{
+    return reinterpret_cast<const C *>(reinterpret_cast<const char *>(base) + off * (uint32_t)sizeof(C));
+}
+
 // Rows (slice g0 + gi, v0 + r) of a unit into LDS (row rho = gi rw + r at
 // rho S), W consecutive values per access (W = 2: 16-byte loads and LDS
 // stores of complex64, N and S even, so every row starts on an even element
@@ -72,7 +84,7 @@ __host__ __device__ inline size_t fused_unit_bytes(int N, int rw, int G, size_t 
 // loads of one trip before it reuses their registers on the next.  The owner
 // changes of the unit's rows are counted while the loads are in flight:
 // every thread with rows to count (threadIdx.x < ng nv) has loads too.
-template <int W, typename C>
+template <int W, bool OFF32, typename C>
 __device__ __forceinline__ void load_unit_rows(const C *__restrict__ in, C *lds, const FftDesc &f,
                                                const XposeDesc &d, const int64_t *abase, int S, int rw, int nv,
                                                int ng, int64_t g0, int64_t v0, int &moved)
@@ -91,7 +103,8 @@ __device__ __forceinline__ void load_unit_rows(const C *__restrict__ in, C *lds,
         at[j] = -1;
         if (gi < ng) {
             at[j] = (gi * rw + r) * S + c * W;
-            const C *p = in + abase[gi] + (v0 + r) * d.a_sv + c * W;
+            const C *p = OFF32 ? at_off32(in, (uint32_t)abase[gi] + (uint32_t)(v0 + r) * (uint32_t)d.a_sv + c * W)
+                               : in + abase[gi] + (v0 + r) * d.a_sv + c * W;
             if constexpr (W == 2) {
                 const xf4 w = gld_nt(reinterpret_cast<const xf4 *>(p));
                 val[j][0] = mk<C>(w.x, w.y);
@@ -131,7 +144,7 @@ __device__ __forceinline__ void load_unit_rows(const C *__restrict__ in, C *lds,
 // u = k, v = v0 + r).  Group e = (gi N + k) nv / W + r / W, W consecutive v
 // per access (W = 2: 16-byte stores of complex64, nv and every run start
 // even).
-template <int W, typename C>
+template <int W, bool OFF32, typename C>
 __device__ __forceinline__ void store_unit_runs(C *__restrict__ out, const C *lds, const XposeDesc &d,
                                                 const int64_t *bbase, int N, int S, int rw, int nv, int ng,
                                                 int64_t v0, typename RealOf<C>::type scale, bool do_scale)
@@ -148,7 +161,8 @@ __device__ __forceinline__ void store_unit_runs(C *__restrict__ out, const C *ld
             q[w] = lds[(gi * rw + r * W + w) * S + k];
             if (do_scale) q[w] = cscale(q[w], scale);
         }
-        C *p = out + bbase[gi] + (int64_t)k * d.b_su + v0 + r * W;
+        C *p = OFF32 ? at_off32(out, (uint32_t)bbase[gi] + (uint32_t)k * (uint32_t)d.b_su + (uint32_t)v0 + r * W)
+                     : out + bbase[gi] + (int64_t)k * d.b_su + v0 + r * W;
         if constexpr (W == 2) {
             const xf4 w = {q[0].x, q[0].y, q[1].x, q[1].y};
             gst_nt(w, reinterpret_cast<xf4 *>(p));
@@ -177,10 +191,11 @@ struct NoHook {
 // TW_LDS: the twiddle table is staged in LDS (the caller checked unit_tw_fits
 // and sized the LDS block with it).  LEAN: the step's radices are 2, 3, 4 and
 // 5 only (the caller made sure), so the larger passes are not compiled in.
-// hook() runs once the unit's rows are in LDS, after a barrier that every
+// OFF32: `in` and `out` each hold fewer than 2^32 bytes (the caller made
+// sure), and HBM addresses are formed from 32-bit offsets.  hook() runs once the unit's rows are in LDS, after a barrier that every
 // thread passed after entering the unit; no HBM access of the unit's is in
 // flight then except the owner-count atomics.
-template <typename C, int DIR, bool TW_LDS, bool LEAN = false, typename Hook = NoHook>
+template <typename C, int DIR, bool TW_LDS, bool LEAN = false, bool OFF32 = false, typename Hook = NoHook>
 __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__restrict__ out, const FftDesc &f,
                                                const XposeDesc &d, int rw, int G, int64_t unit,
                                                typename RealOf<C>::type scale, bool do_scale, unsigned char *smem,
@@ -217,12 +232,12 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
     int moved = 0;
     if constexpr (sizeof(C) == 8) {
         if (N % 2 == 0) {
-            load_unit_rows<2>(in, lds, f, d, abase, S, rw, nv, ng, g0, v0, moved);
+            load_unit_rows<2, OFF32>(in, lds, f, d, abase, S, rw, nv, ng, g0, v0, moved);
         } else {
-            load_unit_rows<1>(in, lds, f, d, abase, S, rw, nv, ng, g0, v0, moved);
+            load_unit_rows<1, OFF32>(in, lds, f, d, abase, S, rw, nv, ng, g0, v0, moved);
         }
     } else {
-        load_unit_rows<1>(in, lds, f, d, abase, S, rw, nv, ng, g0, v0, moved);
+        load_unit_rows<1, OFF32>(in, lds, f, d, abase, S, rw, nv, ng, g0, v0, moved);
     }
     hook();
     if constexpr (TW_LDS) {
@@ -269,12 +284,12 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
     // (complex64: every run then starts on an even element)
     if constexpr (sizeof(C) == 8) {
         if (d.Nv % 2 == 0 && rw % 2 == 0) {
-            store_unit_runs<2>(out, lds, d, bbase, N, S, rw, nv, ng, v0, scale, do_scale);
+            store_unit_runs<2, OFF32>(out, lds, d, bbase, N, S, rw, nv, ng, v0, scale, do_scale);
         } else {
-            store_unit_runs<1>(out, lds, d, bbase, N, S, rw, nv, ng, v0, scale, do_scale);
+            store_unit_runs<1, OFF32>(out, lds, d, bbase, N, S, rw, nv, ng, v0, scale, do_scale);
         }
     } else {
-        store_unit_runs<1>(out, lds, d, bbase, N, S, rw, nv, ng, v0, scale, do_scale);
+        store_unit_runs<1, OFF32>(out, lds, d, bbase, N, S, rw, nv, ng, v0, scale, do_scale);
     }
     __syncthreads();  // the LDS block may be reused by the caller's next unit
 }
