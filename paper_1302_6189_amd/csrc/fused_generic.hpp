@@ -16,6 +16,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "cplx.hpp"
 #include "fft_generic.hpp"
 #include "kernels.hpp"
@@ -31,20 +33,54 @@ constexpr int kUnitItems = 16;  // loads in flight per thread while a unit is st
 // on the LDS banks)
 __host__ __device__ inline int unit_pitch(int N, size_t esz) { return esz == 8 && N % 2 == 0 ? N + 2 : N + 1; }
 
-// Shape of a fused unit for rows of length N: RW rows per slice (a power of
-// two covering the v extent when it can) and G slices, so that a unit holds at
-// most `budget` values with their padding (4096 complex64, 2048 complex128)
-// and every row keeps at least one lane of the 256-thread group.
+// Shape of a fused unit for rows of length N: RW rows consecutive in v per
+// slice and G slices (RW G rows, at most kThreads of them, holding at most
+// `budget` values with their padding: 4096 complex64, 2048 complex128; each
+// row gets a power of two of lanes, unit_lanes, with at most 16 values per
+// lane).  RW is the whole v extent when it fits (a slice's outputs are then
+// one contiguous block), else a multiple of 16 (runs of whole 128-byte
+// lines for complex64), else the largest power of two that fits; among
+// those the shape with the fewest units, ceil(N_v / RW) ceil(slices / G),
+// is taken (ties: longer runs).  Each unit is one chain of loads, barriers,
+// passes and stores, so fuller units mean fewer chains; shorter runs would
+// write partial lines.
+inline int unit_lanes(int rows)
+{
+    int lanes = 1;
+    while (lanes * 2 * rows <= kThreads) lanes *= 2;
+    return lanes;
+}
+
 inline void fused_unit_shape(int N, size_t esz, int64_t Nv, int64_t nslices, int budget, int *rw, int *G)
 {
     budget = budget < kUnitItems * kThreads ? budget : kUnitItems * kThreads;  // one load pass per unit
     const int P = unit_pitch(N, esz);
-    int r = 1;
-    while (r * 2 <= 256 && (int64_t)r * 2 * P <= budget && r * 2 <= 2 * Nv - 1) r *= 2;
-    int g = 1;
-    while (g * 2 * r <= 256 && (int64_t)g * 2 * r * P <= budget && g * 2 <= 2 * nslices - 1) g *= 2;
-    *rw = r;
-    *G = g;
+    int maxrows = budget / P < kThreads ? budget / P : kThreads;
+    // rows such that every row keeps at least ceil(N / 16) lanes
+    while (maxrows > 1 && N > 16 * unit_lanes(maxrows)) --maxrows;
+    if (maxrows < 1) maxrows = 1;
+    int64_t best = -1;
+    int br = 1, bg = 1;
+    auto consider = [&](int r) {
+        const int64_t g = std::min<int64_t>(maxrows / r, nslices);
+        const int64_t units = ((Nv + r - 1) / r) * ((nslices + g - 1) / g);
+        if (best < 0 || units < best || (units == best && r > br)) {
+            best = units;
+            br = r;
+            bg = (int)g;
+        }
+    };
+    if (Nv <= maxrows) {
+        consider((int)Nv);
+    } else if (maxrows >= 16) {
+        for (int r = 16; r <= maxrows; r += 16) consider(r);
+    } else {
+        int r = 1;
+        while (r * 2 <= maxrows) r *= 2;
+        consider(r);
+    }
+    *rw = br;
+    *G = bg;
 }
 
 // Units may stage the row length's twiddle table in LDS when its N entries
@@ -252,10 +288,13 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
             atomicAdd(d.counter + (unit % kCountSlots) * kCountStride, (unsigned long long)moved);
     }
     __syncthreads();
-    const int lanes = kThreads / (G * rw);
+    // each of the G rw rows gets a power of two of lanes; threads past the
+    // last row take part in the barriers only (lane N: no butterfly)
+    const int lanes = 1 << (31 - __clz(kThreads / (G * rw)));
     const int row = threadIdx.x / lanes;
-    const int lane = threadIdx.x - row * lanes;
-    C *lrow = lds + row * S;
+    const bool in_row = row < G * rw;
+    const int lane = in_row ? threadIdx.x - row * lanes : N;
+    C *lrow = lds + (in_row ? row : 0) * S;
     const C *tw = TW_LDS ? static_cast<const C *>(ltw) : reinterpret_cast<const C *>(f.tw);
     // a row's lanes are consecutive threads, a power of two of them: at most
     // 64 sit in one wave, and the passes then synchronise that wave only (the
