@@ -78,8 +78,8 @@ constexpr int kWaitVmcnt0 = 0x0F70;
 
 // units per claim of the level counter, and the level's last units claimed
 // one at a time (this many per work-group of the grid)
-constexpr int kClaimUnits = 4;
-constexpr int kClaimTail = 2;
+constexpr int kClaimUnits = 3;
+constexpr int kClaimTail = 4;
 
 // real-time clock ticks (100 MHz) a work-group may wait at one barrier
 constexpr unsigned long long kWaitTicks = 200000000ull;
