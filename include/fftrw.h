@@ -460,6 +460,20 @@ int fft_batch_destroy(fft_batch_t batch);
 int fft_autotune(int n, const fft_item_desc *items, const char *cache_path,
                  unsigned flags);
 
+/*
+ * fft_fused_unit_shape -- the work-group unit of a step whose 1-D FFTs along
+ * u (rows of N points, Eq. (1)) are fused with the transpose that follows
+ * (Fig. 4): rw rows consecutive in v, the next layout's fastest axis, in each
+ * of G slices.  The plans and the batched form use this rule; the call is
+ * for tests and tools, host only (no device needed).  esz: bytes per complex
+ * value, 8 (complex64: units of at most 4096 values with padding) or 16
+ * (complex128: 2048).  Nv: extent of v; nslices: number of batch slices.
+ * The unit count of the step is ceil(Nv / rw) * ceil(nslices / G).  Returns
+ * FFTRW_OK, or FFTRW_E_ARG for N < 2, Nv < 1, nslices < 1, another esz or
+ * a null output.
+ */
+int fft_fused_unit_shape(int N, int esz, int64_t Nv, int64_t nslices, int *rw, int *G);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char *fft_last_error(void);
 

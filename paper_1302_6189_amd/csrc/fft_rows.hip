@@ -1,7 +1,10 @@
 // fft_rows.hip -- stand-alone launch of the generic row FFT (fft_generic.hpp)
-// for 2,3,5-smooth lengths, and the FP64 twiddle table w_N^e it reads.
+// for 2,3,5-smooth lengths, the FP64 twiddle table w_N^e it reads, and the
+// fused unit's shape rule exported for tests (fft_fused_unit_shape).
 #include <hip/hip_runtime.h>
 
+#include "../../include/fftrw.h"
+#include "errors.hpp"
 #include "fft_generic.hpp"
 #include "fused_generic.hpp"
 
@@ -137,3 +140,13 @@ hipError_t launch_fft_xpose_generic(const FftDesc &f, const XposeDesc &d, bool f
 }
 
 }  // namespace fftrw
+
+extern "C" int fft_fused_unit_shape(int N, int esz, int64_t Nv, int64_t nslices, int *rw, int *G)
+{
+    fftrw::g_last_error.clear();
+    if (N < 2 || Nv < 1 || nslices < 1 || (esz != 8 && esz != 16) || !rw || !G)
+        return fftrw::fail(FFTRW_E_ARG, "fft_fused_unit_shape: N >= 2, Nv >= 1, nslices >= 1, esz 8 or 16, "
+                                        "non-null outputs");
+    fftrw::fused_unit_shape(N, (size_t)esz, Nv, nslices, esz == 16 ? 2048 : 4096, rw, G);
+    return FFTRW_OK;
+}

@@ -56,6 +56,8 @@ _SIGNATURES = {
     "fft_comm_volume": (ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, _i8p, ctypes.c_int,
                                        _i64p, _i64p, _i64p]),
     "fft_rowsplit_volume": (ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, _i8p, _i64p, _i64p]),
+    "fft_fused_unit_shape": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "fft_pair_counts": (ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, _i8p, _i8p, _i64p]),
     "fft_transpose_volumes": (ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, _i64p]),
     "fft_order_count": (ctypes.c_int64, [ctypes.c_int]),
@@ -192,6 +194,13 @@ def fft_rowsplit_volume(dims, P, order):
     tot = ctypes.c_int64()
     _check(lib().fft_rowsplit_volume(M, _dims(dims), int(P), _order(order), per, ctypes.byref(tot)))
     return list(per), tot.value
+
+
+def fft_fused_unit_shape(N, Nv, nslices, esz=8):
+    """(rw, G) of the fused FFT + transpose unit for rows of N points."""
+    rw, G = ctypes.c_int(), ctypes.c_int()
+    _check(lib().fft_fused_unit_shape(int(N), int(esz), int(Nv), int(nslices), ctypes.byref(rw), ctypes.byref(G)))
+    return rw.value, G.value
 
 
 def fft_pair_counts(dims, P, perm_a, perm_b):
