@@ -5,12 +5,13 @@
 // units -- a block of rows of one FFT step, or a tile of one transpose --
 // grouped into stage levels: level s holds stage s of every item that has
 // one.  One grid of work-groups, sized to stay resident, sweeps the levels:
-// inside a level units are taken from the level's atomic counter.  A
-// work-group leaving a level adds the number of units it completed there to
-// the level's done counter (after a release at device scope) and waits until
-// the counter holds every unit of the level (then acquires, so data written
-// on one XCD is seen on the others), which keeps every item's FFT ->
-// transpose -> FFT order.  Counting units rather than arrivals means no
+// inside a level units are taken from the level's atomic counter, a few
+// consecutive units per claim.  A work-group leaving a level adds the number
+// of units it completed there to the level's done counter (after a release
+// at device scope, issued by one wave for the group) and waits until the
+// counter holds every unit of the level (then acquires, so data written on
+// one XCD is seen on the others), which keeps every item's FFT -> transpose
+// -> FFT order.  Counting units rather than arrivals means no
 // work-group waits for one that has not started: a unit is only ever claimed
 // by a running work-group, and a level is left only once all its units are
 // claimed, so the wait ends whether or not the whole grid is resident

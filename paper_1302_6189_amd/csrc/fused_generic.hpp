@@ -245,10 +245,12 @@ __device__ __forceinline__ void fft_xpose_unit(const C *__restrict__ in, C *__re
     const size_t tw_bytes = TW_LDS ? (((size_t)N * sizeof(C) + 15) & ~(size_t)15) : 0;
     int64_t *abase = reinterpret_cast<int64_t *>(smem + rows_bytes + tw_bytes);
     int64_t *bbase = abase + G;
-    const int64_t tiles_v = (d.Nv + rw - 1) / rw;
-    const int64_t tv = unit % tiles_v;
-    const int64_t g0 = (unit / tiles_v) * G;
-    const int64_t v0 = tv * rw;
+    // in 32 bits: the plans keep every size at most 4096, the slice count and
+    // a step's unit count below 2^31
+    const uint32_t tiles_v = ((uint32_t)d.Nv + (uint32_t)rw - 1) / (uint32_t)rw;
+    const uint32_t tv = (uint32_t)unit % tiles_v;
+    const int64_t g0 = (int64_t)((uint32_t)unit / tiles_v) * G;
+    const int64_t v0 = (int64_t)tv * rw;
     const int nv = (int)min<int64_t>(rw, d.Nv - v0);
     const int ng = (int)min<int64_t>(G, d.nslices - g0);
     for (int gi = threadIdx.x; gi < ng; gi += kThreads) {
