@@ -108,9 +108,18 @@ template <int N, class RL> struct PassInfo<N, RL, 0> {
     static constexpr int tw_off = 0;
 };
 
-// twiddle v[b R + i] *= w^{i k} for the thread's butterflies of pass P
-template <int N, int E, int DIR, class RL, int P, typename C>
-__device__ __forceinline__ void apply_twiddles(C *v, int lane, const C *tw)
+// The twiddles w^{i k} of the thread's butterflies in pass P (k = j mod Ns
+// for butterfly j = lane B + b), read from the pass's table.  They depend on
+// the lane only, so run_passes loads each pass's twiddles one pass ahead,
+// before the exchange that precedes it; they arrive while the exchange runs.
+template <int N, int E, class RL, int P, typename C> struct PassTwiddles {
+    static constexpr int R = PassInfo<N, RL, P>::R;
+    static constexpr int B = E / R;
+    C t[PassInfo<N, RL, P>::Ns > 1 ? B : 1][R - 1];
+};
+
+template <int N, int E, class RL, int P, typename C>
+__device__ __forceinline__ void load_twiddles(PassTwiddles<N, E, RL, P, C> &w, int lane, const C *tw)
 {
     using PI = PassInfo<N, RL, P>;
     constexpr int R = PI::R, B = E / R;
@@ -121,8 +130,22 @@ __device__ __forceinline__ void apply_twiddles(C *v, int lane, const C *tw)
             const int k = j % PI::Ns;
             const C *t = tw + PI::tw_off + k * (R - 1);
 #pragma unroll
-            for (int i = 1; i < R; ++i) v[b * R + i] = twmul<DIR>(v[b * R + i], t[i - 1]);
+            for (int i = 1; i < R; ++i) w.t[b][i - 1] = t[i - 1];
         }
+    }
+}
+
+// twiddle v[b R + i] *= w^{i k} for the thread's butterflies of pass P
+template <int N, int E, int DIR, class RL, int P, typename C>
+__device__ __forceinline__ void apply_twiddles(C *v, const PassTwiddles<N, E, RL, P, C> &w)
+{
+    using PI = PassInfo<N, RL, P>;
+    constexpr int R = PI::R, B = E / R;
+    if constexpr (PI::Ns > 1) {
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int i = 1; i < R; ++i) v[b * R + i] = twmul<DIR>(v[b * R + i], w.t[b][i - 1]);
     }
 }
 
@@ -160,15 +183,29 @@ __device__ __forceinline__ void exchange(C *v, C *row, int lane)
     __syncthreads();
 }
 
+// passes P.. of the thread's E values; w holds pass P's twiddles (loaded by
+// the caller), pass P + 1's are loaded before the exchange between the two
 template <int N, int E, int DIR, class RL, int P, typename C>
-__device__ __forceinline__ void run_passes(C *v, C *row, int lane, const C *tw)
+__device__ __forceinline__ void run_passes(C *v, C *row, int lane, const C *tw,
+                                           const PassTwiddles<N, E, RL, P, C> &w)
 {
-    apply_twiddles<N, E, DIR, RL, P>(v, lane, tw);
+    apply_twiddles<N, E, DIR, RL, P>(v, w);
     butterflies<E, DIR, RL, P>(v);
     if constexpr (P + 1 < RL::n) {
+        PassTwiddles<N, E, RL, P + 1, C> wn;
+        load_twiddles<N, E, RL, P + 1>(wn, lane, tw);
         exchange<N, E, RL, P>(v, row, lane);
-        run_passes<N, E, DIR, RL, P + 1>(v, row, lane, tw);
+        run_passes<N, E, DIR, RL, P + 1>(v, row, lane, tw, wn);
     }
+}
+
+// all passes, from the first (whose twiddles are all 1: Ns = 1)
+template <int N, int E, int DIR, class RL, typename C>
+__device__ __forceinline__ void run_passes(C *v, C *row, int lane, const C *tw)
+{
+    PassTwiddles<N, E, RL, 0, C> w0;
+    load_twiddles<N, E, RL, 0>(w0, lane, tw);
+    run_passes<N, E, DIR, RL, 0>(v, row, lane, tw, w0);
 }
 
 template <typename C, int N, int E, int DIR, class RL>
@@ -204,7 +241,7 @@ __global__ void __launch_bounds__(kThreads)
             for (int e = 0; e < E; ++e) v[e] = mk<C>(0, 0);
         }
     }
-    run_passes<N, E, DIR, RL, 0>(v, lds + lrow * (N + N / 16), lane, tw);
+    run_passes<N, E, DIR, RL>(v, lds + lrow * (N + N / 16), lane, tw);
     {   // last pass outputs straight to HBM at j + i N/R
         using PI = PassInfo<N, RL, NP - 1>;
         constexpr int R = PI::R, B = E / R;
@@ -308,7 +345,7 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
         }
     }
 
-    run_passes<N, E, DIR, RL, 0>(v, lds + r * (N + N / 16), lane, tw);
+    run_passes<N, E, DIR, RL>(v, lds + r * (N + N / 16), lane, tw);
     {   // last pass outputs (row r, k = j + i N/R) into the staging block
         using PI = PassInfo<N, RL, NP - 1>;
         constexpr int R = PI::R, B = E / R;
