@@ -366,6 +366,29 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
     const int npair = (nv + 1) / 2;
     const bool wide = (d.Nv & 1) == 0;
     C *dstb = out + bbase + v0;
+    if constexpr (sizeof(C) == 8 && N * HP % NT == 0) {
+        if (nv == RW && wide) {
+            // a full tile in 16-byte pairs, with no branch per run: every LDS
+            // read of the thread is issued before the first store waits
+            using V4 = typename Vec2<float2>::type;
+            constexpr int IT = N * HP / NT;
+            V4 w[IT];
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int idx = threadIdx.x + it * NT;
+                const int r0 = 2 * (idx % HP), k = idx / HP;
+                const C a0 = lds[k * SROW + r0], a1 = lds[k * SROW + r0 + 1];
+                w[it] = V4{a0.x, a0.y, a1.x, a1.y};
+            }
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int idx = threadIdx.x + it * NT;
+                const int r0 = 2 * (idx % HP), k = idx / HP;
+                __builtin_nontemporal_store(w[it], reinterpret_cast<V4 *>(dstb + (int64_t)k * d.b_su + r0));
+            }
+            goto stored;
+        }
+    }
     for (int idx = threadIdx.x; idx < N * HP; idx += NT) {
         const int rp = idx % HP;
         const int k = idx / HP;
@@ -392,6 +415,7 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
             st_nt(p, a0);
         }
     }
+stored:
     if constexpr (RW > 64) {
         if (d.count) {
             for (int off = 32; off > 0; off >>= 1) moved += __shfl_xor(moved, off);
