@@ -289,24 +289,16 @@ __global__ void __launch_bounds__((FusedThreads<N, E>::value))
     __shared__ C lds[LDS_FFT > LDS_STG ? LDS_FFT : LDS_STG];
     __shared__ int moved_wg;
 
-    const int64_t tiles_v = (d.Nv + RW - 1) / RW;
-    const int64_t tv = blockIdx.x % tiles_v;
-    const int64_t slice = blockIdx.x / tiles_v;
-    const int64_t v0 = tv * RW;
+    // block coordinates in 32 bits (sizes are at most 4096, a launch has
+    // fewer than 2^31 groups): they come before the first row load
+    const uint32_t tiles_v = ((uint32_t)d.Nv + RW - 1) / RW;
+    const uint32_t tv = blockIdx.x % tiles_v;
+    const uint32_t slice = blockIdx.x / tiles_v;
+    const int64_t v0 = (int64_t)tv * RW;
     const int nv = (int)min<int64_t>(RW, d.Nv - v0);
     int bc[3] = {0, 0, 0};
     int64_t abase = 0, bbase = 0;
-    {
-        int64_t sl = slice;
-        for (int i = 0; i < d.nbat; ++i) {
-            const int64_t q = sl / d.bsize[i];
-            const int64_t ci = sl - q * d.bsize[i];
-            sl = q;
-            bc[i] = (int)ci;
-            abase += ci * d.ba[i];
-            bbase += ci * d.bb[i];
-        }
-    }
+    slice_coords(d, slice, bc, &abase, &bbase);
     const int lane = threadIdx.x % L;
     const int r = threadIdx.x / L;
     const bool active = r < nv;
