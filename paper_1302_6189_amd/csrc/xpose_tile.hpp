@@ -31,6 +31,7 @@
 namespace fftrw {
 
 constexpr int kMaxG = 256;
+constexpr int kTileBatch = 8;  // rows a thread loads (or stores) before it waits
 
 typedef float xf4 __attribute__((ext_vector_type(4)));
 typedef float xf2 __attribute__((ext_vector_type(2)));
@@ -156,7 +157,8 @@ __device__ __forceinline__ int tile_moved(const XposeDesc &d, int64_t g0, int ng
     return moved;
 }
 
-// LDS bytes of a tile, 16-byte aligned
+// LDS bytes of a tile, 16-byte aligned; launchers reserve 16 more bytes
+// after it (xpose_tile writes the loads of items past the tile there)
 __host__ __device__ inline size_t xpose_tile_bytes(const XposeDesc &d, size_t esz)
 {
     size_t b = (size_t)d.G * d.TV * (d.TU + 1) * esz;
@@ -192,70 +194,103 @@ __device__ __forceinline__ void xpose_tile(const C *__restrict__ in, C *__restri
             atomicAdd(d.counter + (tile_index % kCountSlots) * kCountStride, (unsigned long long)moved);
     }
 
-    // load: rows (g, v) of contiguous u-values
+    // load: rows (g, v) of contiguous u-values.  A thread's rows are taken
+    // kTileBatch at a time, every load of a batch issued before any value
+    // goes to LDS (a loop that writes each value as it arrives runs the
+    // thread's loads one HBM round trip at a time).
     {
         const int per_row = TU / VU;
         const int tx = threadIdx.x % per_row;
         const int ty = threadIdx.x / per_row;
         const int ystep = kThreads / per_row;
         const int nrow = ng * nv;
+        const int iu = tx * VU;
+        const int spare = d.G * TV * ldt;  // first element after the tile
         int gcur = -1;
         int64_t abase = 0;
-        for (int r = ty; r < nrow; r += ystep) {
-            const int g = r / nv;
-            const int iv = r - g * nv;
-            if (g != gcur) {
-                int c[3];
-                int64_t bb;
-                slice_coords(d, g0 + g, c, &abase, &bb);
-                gcur = g;
-            }
-            const int iu = tx * VU;
-            if (iu < nu) {
-                const C *p = in + abase + (v0 + iv) * d.a_sv + u0 + iu;
-                C *trow = tile + (g * TV + iv) * ldt + iu;
-                if constexpr (VU == 2) {
-                    xf4 w = gld_nt(reinterpret_cast<const xf4 *>(p));
-                    trow[0] = mk<C>(w.x, w.y);
-                    trow[1] = mk<C>(w.z, w.w);
-                } else {
-                    trow[0] = xld(p);
+        for (int rb = ty; rb < nrow; rb += kTileBatch * ystep) {
+            C val[kTileBatch][VU];
+            int at[kTileBatch];
+            // every item loads and writes, so that no load is left pending
+            // from one trip to the next: an item past the tile loads an
+            // element of the tile again (clamped) and writes it to the spare
+            // 16 bytes after the tile, which the launchers reserve
+#pragma unroll
+            for (int j = 0; j < kTileBatch; ++j) {
+                const int r = rb + j * ystep;
+                const bool ok = r < nrow && iu < nu;
+                const int rc = r < nrow ? r : nrow - 1;
+                const int iuc = iu < nu ? iu : 0;
+                const int g = rc / nv;
+                const int iv = rc - g * nv;
+                if (g != gcur) {
+                    int c[3];
+                    int64_t bb;
+                    slice_coords(d, g0 + g, c, &abase, &bb);
+                    gcur = g;
                 }
+                const C *p = in + abase + (v0 + iv) * d.a_sv + u0 + iuc;
+                at[j] = ok ? (g * TV + iv) * ldt + iu : spare;
+                if constexpr (VU == 2) {
+                    const xf4 w = gld_nt(reinterpret_cast<const xf4 *>(p));
+                    val[j][0] = mk<C>(w.x, w.y);
+                    val[j][1] = mk<C>(w.z, w.w);
+                } else {
+                    val[j][0] = xld(p);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kTileBatch; ++j) {
+#pragma unroll
+                for (int w = 0; w < VU; ++w) tile[at[j] + w] = val[j][w];
             }
         }
     }
     __syncthreads();
 
-    // store: rows (g, u) of contiguous v-values
+    // store: rows (g, u) of contiguous v-values, kTileBatch rows at a time,
+    // every LDS read of a batch issued before its first store
     {
         const int per_row = TV / VV;
         const int tx = threadIdx.x % per_row;
         const int ty = threadIdx.x / per_row;
         const int ystep = kThreads / per_row;
         const int nrow = ng * nu;
+        const int iv = tx * VV;
         int gcur = -1;
         int64_t bbase = 0;
-        for (int r = ty; r < nrow; r += ystep) {
-            const int g = r / nu;
-            const int iu = r - g * nu;
-            if (g != gcur) {
-                int c[3];
-                int64_t ab;
-                slice_coords(d, g0 + g, c, &ab, &bbase);
-                gcur = g;
-            }
-            const int iv = tx * VV;
-            if (iv < nv) {
-                C *p = out + bbase + (u0 + iu) * d.b_su + v0 + iv;
-                const C *tcol = tile + (g * TV + iv) * ldt + iu;
-                if constexpr (VV == 2) {
-                    const C a0 = tcol[0], a1 = tcol[ldt];
-                    xf4 w = {a0.x, a0.y, a1.x, a1.y};
-                    gst_nt(w, reinterpret_cast<xf4 *>(p));
-                } else {
-                    xst(p, tcol[0]);
+        for (int rb = ty; rb < nrow; rb += kTileBatch * ystep) {
+            C val[kTileBatch][VV];
+            C *dst[kTileBatch];
+#pragma unroll
+            for (int j = 0; j < kTileBatch; ++j) {
+                const int r = rb + j * ystep;
+                dst[j] = nullptr;
+                if (r < nrow && iv < nv) {
+                    const int g = r / nu;
+                    const int iu = r - g * nu;
+                    if (g != gcur) {
+                        int c[3];
+                        int64_t ab;
+                        slice_coords(d, g0 + g, c, &ab, &bbase);
+                        gcur = g;
+                    }
+                    dst[j] = out + bbase + (u0 + iu) * d.b_su + v0 + iv;
+                    const C *tcol = tile + (g * TV + iv) * ldt + iu;
+                    val[j][0] = tcol[0];
+                    if constexpr (VV == 2) val[j][1] = tcol[ldt];
                 }
             }
+#pragma unroll
+            for (int j = 0; j < kTileBatch; ++j)
+                if (dst[j]) {
+                    if constexpr (VV == 2) {
+                        const xf4 w = {val[j][0].x, val[j][0].y, val[j][1].x, val[j][1].y};
+                        gst_nt(w, reinterpret_cast<xf4 *>(dst[j]));
+                    } else {
+                        xst(dst[j], val[j][0]);
+                    }
+                }
         }
     }
     __syncthreads();  // the LDS block may be reused by the caller's next unit
