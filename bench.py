@@ -115,10 +115,12 @@ def time_fwd(plan, x, y, stream, reps, warm=3):
     return e0.elapsed_time(e1) / reps
 
 
-def precision_forms(reps):
-    """256^3 complex64 (P = 64, best order): FP32 Stockham against the split
-    FP16 / BF16 / BF16x3 MFMA forms; time per transform and errors against the
-    FP64 oracle on uniform and log-uniform inputs.  Errors are computed first;
+def precision_forms(reps, dims=(256, 256, 256), P=64):
+    """A 3-D complex64 transform (256^3 at P = 64, or 512^3 at P = 4096; best
+    order): FP32 Stockham against the split FP16 / BF16 / BF16x3 MFMA forms
+    (256-point rows as two radix-16 contractions, 512-point rows as two such
+    halves and a radix-2 combination); time per transform and errors against
+    the FP64 oracle on uniform and log-uniform inputs.  Errors are computed first;
     the timings follow back to back (the host-side error checks leave the GPU
     idle for seconds, and a short timed run right after them would include the
     clock ramp), each form timed three times, interleaved, median reported."""
@@ -127,9 +129,8 @@ def precision_forms(reps):
 
     from oracle import dft, orders
     from paper_1302_6189_amd import fftrw, inputs
-    dims = (256, 256, 256)
     T = math.prod(dims)
-    order = fftrw.fft_order_search(dims, 64)["best_order"]
+    order = fftrw.fft_order_search(dims, P)["best_order"]
     seq = orders.fft_axis_sequence(order)
     data = {}
     for kind, seed in (("uniform", 4), ("log_uniform", 40)):
@@ -142,8 +143,8 @@ def precision_forms(reps):
     yd = torch.empty_like(xd)
     res, plans = {}, {}
     for name, prec in forms:
-        plan = fftrw.Plan(dims, 64, order, precision=prec, flags=fftrw.FLAG_SEPARATE)
-        fplan = fftrw.Plan(dims, 64, order, precision=prec, flags=fftrw.FLAG_FUSED_FFT)
+        plan = fftrw.Plan(dims, P, order, precision=prec, flags=fftrw.FLAG_SEPARATE)
+        fplan = fftrw.Plan(dims, P, order, precision=prec, flags=fftrw.FLAG_FUSED_FFT)
         plans[name] = (plan, fplan)
         entry = {}
         for kind, (x, ref) in data.items():
@@ -191,7 +192,8 @@ def precision_forms(reps):
         fplan.destroy()
     del xd, yd
     res["timing"] = f"median of 3 interleaved runs of {n} transforms after 20 warm-up transforms"
-    res["workload"] = "3-D complex64 FFT 256x256x256, P=64, order " + fftrw.order_to_str(order)
+    res["workload"] = (f"3-D complex64 FFT {'x'.join(map(str, dims))}, P={P}, order "
+                       + fftrw.order_to_str(order))
     return res
 
 
@@ -495,6 +497,8 @@ def main():
     if not args.no_forms:
         torch.cuda.empty_cache()
         out["precision_form"] = precision_forms(args.steps)
+        torch.cuda.empty_cache()
+        out["precision_form_512cube"] = precision_forms(args.steps, (512, 512, 512), 4096)
         torch.cuda.empty_cache()
         out["batched_form"] = batched_form(max(5, args.steps // 2))
     if not args.no_cpu_baseline:

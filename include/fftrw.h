@@ -237,7 +237,8 @@ int fft_compare_models(double N, double P, double *out);
  *   order: M*M int8 as above, or NULL for the best order of fft_order_search
  *          (literal ownership, lowest canonical index on ties).
  *   dtype: FFTRW_C64 or FFTRW_C128.   precision: FFTRW_PREC_*; the split MFMA
- *          forms need dtype C64 and every FFT axis a power of two >= 16.
+ *          forms need dtype C64; axes of 256 and 512 points run on MFMA,
+ *          other axes keep the FP32 Stockham kernels.
  *   flags: FFTRW_FLAG_*.
  * Row lengths: every dims[i] must factor into 2, 3, 5 and be <= 4096.
  * 1 <= P <= T.  Steps at level M of Eq. (13) (P > T / N_last, rows split
@@ -250,8 +251,8 @@ int fft_compare_models(double N, double P, double *out);
  * FFT step runs fused with the transpose that follows it when every step
  * qualifies (power-of-two rows of 16..512 points for C64, 16..256 for C128,
  * whose work-group's run along the next layout's last axis fits that axis;
- * other 2,3,5-smooth rows up to 4095 points for C64, 2047 for C128; 256-point
- * rows of the split MFMA forms); otherwise, and for execs with in == out, the
+ * other 2,3,5-smooth rows up to 4095 points for C64, 2047 for C128; 256- and
+ * 512-point rows of the split MFMA forms); otherwise, and for execs with in == out, the
  * steps and transposes run as separate kernels.  Results are bit-identical
  * either way; fft_plan_describe's text starts with "fused|" when it fuses.
  * The plan owns its device workspace (fft_workspace_bytes) and twiddle

@@ -34,10 +34,10 @@ hipError_t launch_fft_xpose_generic(const FftDesc &f, const XposeDesc &d, bool f
                                     void *out, double scale, hipStream_t s);
 hipError_t launch_fft_xpose_pow2(int N, bool fp64, const void *tw, const XposeDesc &fx, int dir, const void *in,
                                  void *out, double scale, hipStream_t s);
-hipError_t launch_fft256_mfma_xpose(int precision, int dir, const void *tw256, const XposeDesc &d, const void *in,
-                                    void *out, double scale, hipStream_t s);
-hipError_t launch_fft256_mfma(int precision, int dir, const void *tw256, int64_t nrows, const void *in, void *out,
-                              double scale, hipStream_t s);
+hipError_t launch_fft_mfma_xpose(int precision, int dir, int N, const void *twN, const XposeDesc &d, const void *in,
+                                 void *out, double scale, hipStream_t s);
+hipError_t launch_fft_mfma(int precision, int dir, int N, const void *twN, int64_t nrows, const void *in, void *out,
+                           double scale, hipStream_t s);
 hipError_t launch_fft_rows(const FftDesc &d, bool fp64, int dir, const void *in, void *out, double scale,
                            hipStream_t s);
 hipError_t launch_xpose(const XposeDesc &d, size_t esz, const void *in, void *out, hipStream_t s);
@@ -126,12 +126,14 @@ int make_len_desc(fft_plan_impl *pl, i64 N, FftDesc *d, bool generic_rows, const
     std::memset(d, 0, sizeof(*d));
     d->N = (int)N;
     d->nrows = pl->T / N;
-    if (pl->precision != FFTRW_PREC_NATIVE && N == 256) {
-        // two radix-16 DFT contractions on MFMA, generic 256-entry twiddle table
+    if (pl->precision != FFTRW_PREC_NATIVE && (N == 256 || N == 512)) {
+        // two radix-16 DFT contractions on MFMA (per half row for 512, then a
+        // radix-2 combination), generic N-entry twiddle table
         d->mfma = pl->precision;
-        d->npass = 2;
+        d->npass = N == 256 ? 2 : 3;
         d->radix[0] = d->radix[1] = 16;
-        d->tw_count = 256;
+        d->radix[2] = 2;
+        d->tw_count = (int)N;
         return FFTRW_OK;
     }
     if (!generic_rows && pow2_supported((int)N, pl->esz == 16)) {
@@ -307,7 +309,7 @@ int run_fft_desc(fft_plan_impl *pl, const FftDesc &d, int dir, const void *in, v
                  hipStream_t s)
 {
     if (d.mfma) {
-        HIP_TRY(launch_fft256_mfma(d.mfma, dir, d.tw, d.nrows, in, out, scale, s), "mfma fft pass launch");
+        HIP_TRY(launch_fft_mfma(d.mfma, dir, d.N, d.tw, d.nrows, in, out, scale, s), "mfma fft pass launch");
         return FFTRW_OK;
     }
     if (d.pow2) {
@@ -380,7 +382,7 @@ int run_pipeline(fft_plan_impl *pl, const void *in, void *out, hipStream_t s, in
                 HIP_TRY(launch_fft_xpose_pow2(d.N, pl->esz == 16, d.tw, pl->xp[t], dir, src, dst, scale, s),
                         "fused fft+transpose launch");
             else if (pl->fuse_kind[t] == 3)
-                HIP_TRY(launch_fft256_mfma_xpose(d.mfma, dir, d.tw, pl->xp[t], src, dst, scale, s),
+                HIP_TRY(launch_fft_mfma_xpose(d.mfma, dir, d.N, d.tw, pl->xp[t], src, dst, scale, s),
                         "fused mfma fft+transpose launch");
             else
                 HIP_TRY(launch_fft_xpose_generic(d, pl->xp[t], pl->esz == 16, dir, src, dst, scale, s),
@@ -645,8 +647,8 @@ int plan_create(fft_plan_t *plan, int M, const int64_t *dims, int64_t P, const i
     // fusion of every FFT step with its transpose (the default): power-of-two
     // rows of 16..512 (256 in FP64) whose work-group's run of consecutive
     // v-values fits the v axis use the compile-time kernel; 2,3,5-smooth rows
-    // use the generic unit; steps of the split-precision form (256 points) use
-    // the MFMA kernel
+    // use the generic unit; steps of the split-precision form (256 and 512
+    // points) use the MFMA kernel
     if (!(flags & (FFTRW_FLAG_SEPARATE | FFTRW_FLAG_STAGED)) && !generic_rows) {
         const bool fp64 = pl->esz == 16;
         const int nx = (flags & FFTRW_FLAG_LEAVE_PERMUTED) ? M - 1 : M;

@@ -28,7 +28,7 @@ struct FftDesc {
     const void *tw;    // forward twiddles w_N^e, e = 0..N-1 (float2 or double2),
                        // or the per-pass table of the power-of-two kernel
     int pow2;          // 1: compile-time power-of-two kernel (fft_pow2.hip)
-    int mfma;          // > 0: 256-point split-precision MFMA kernel (fft_mfma.hip)
+    int mfma;          // > 0: 256/512-point split-precision MFMA kernel (fft_mfma.hip)
     int tw_count;      // entries in the twiddle table
 };
 

@@ -1,5 +1,7 @@
 """GPU parity of the precision form: 256-point steps as radix-16 DFT
-contractions on FP16/BF16 MFMA with split operands, FP32 accumulation.
+contractions on FP16/BF16 MFMA with split operands, FP32 accumulation;
+512-point steps as two such transforms (even and odd points) and one radix-2
+combination in FP32.
 
 Bounds (relative L2 against the FP64 oracle on the very same complex64 input):
 * FP32 Stockham: 1e-5;
@@ -22,21 +24,22 @@ PRECS = {"f16": (fftrw.PREC_SPLIT_F16, 3e-6), "bf16x3": (fftrw.PREC_SPLIT_BF16X3
          "bf16": (fftrw.PREC_SPLIT_BF16, 2e-5), "fp32": (fftrw.PREC_NATIVE, 1e-5)}
 
 
+@pytest.mark.parametrize("N", [256, 512])
 @pytest.mark.parametrize("name", list(PRECS))
 @pytest.mark.parametrize("kind", ["uniform", "log_uniform"])
-def test_single_256_pass(gpu_lib, name, kind):
+def test_single_pass(gpu_lib, name, kind, N):
     prec, tol = PRECS[name]
-    dims = (1024, 256)
+    dims = (1024, N)
     x = getattr(inputs, kind)(dims, 41, np.complex64)
     plan = fftrw.Plan(dims, 4, "ab->ba", precision=prec)
     if prec != fftrw.PREC_NATIVE:
-        assert plan.describe()[1].startswith("mfma:16x16")
+        assert plan.describe()[1].startswith("mfma:16x16" + ("x2" if N == 512 else "")), plan.describe()
     xd = to_dev(x)
     for direction in (-1, 1):
         yd = empty_dev(dims, np.complex64)
         plan.exec_fft_step(0, direction, xd, yd)
         err = dft.rel_l2(to_host(yd), dft.fft1d_rows(x, sign=direction))
-        print(f"{name} {kind} dir {direction}: rel-L2 {err:.3e}", flush=True)
+        print(f"{name} {kind} N={N} dir {direction}: rel-L2 {err:.3e}", flush=True)
         assert err < tol / 2
 
 
@@ -78,11 +81,13 @@ def test_256cube_precision_forms(gpu_lib, cube256, name, kind, mode):
 
 @pytest.mark.parametrize("name", ["f16", "bf16", "bf16x3"])
 @pytest.mark.parametrize("dims,P,oidx", [((256, 256, 256), 64, 0), ((256, 40, 256), 7, 3),
-                                         ((256, 256, 24, 256), 300, 700), ((256, 27, 256), 5, 0)])
+                                         ((256, 256, 24, 256), 300, 700), ((256, 27, 256), 5, 0),
+                                         ((512, 12, 512), 7, 3), ((512, 27, 256), 5, 0), ((512, 27, 256), 9, 4),
+                                         ((512, 64, 512), 4096, 1)])
 def test_fused_mfma_matches_separate_steps(gpu_lib, name, dims, P, oidx):
-    # the 256-point MFMA transform fused with the transpose that follows runs the
-    # same per-row arithmetic as the separate MFMA step; N_v = 40 and 24 leave
-    # ragged groups of 16 rows
+    # the MFMA transform fused with the transpose that follows runs the same
+    # per-row arithmetic as the separate MFMA step; N_v = 40, 24, 12 and 27
+    # leave ragged groups of 16 (256-point rows) or 8 rows (512-point rows)
     prec, _ = PRECS[name]
     order = fftrw.fft_order_at(len(dims), oidx)
     x = inputs.uniform(dims, 44, np.complex64)
@@ -102,3 +107,37 @@ def test_fused_mfma_matches_separate_steps(gpu_lib, name, dims, P, oidx):
             # odd (27) and ragged (40) next-layout axes: against the oracle too
             ref = dft.fftn_direct(x, orders.fft_axis_sequence(order))
             assert dft.rel_l2(to_host(a), ref) < PRECS[name][1], name
+
+
+@pytest.fixture(scope="module")
+def rows512():
+    dims = (512, 64, 512)
+    order = fftrw.fft_order_search(dims, 4096)["best_order"]
+    x = inputs.uniform(dims, 45, np.complex64)
+    return dims, order, x, dft.fftn_direct(x, orders.fft_axis_sequence(order))
+
+
+@pytest.mark.parametrize("mode", ["fused", "separate"])
+@pytest.mark.parametrize("name", list(PRECS))
+def test_512_rows_precision_forms(gpu_lib, rows512, name, mode):
+    # two axes of 512 points on MFMA (even/odd halves and the radix-2
+    # combination), the 64-point axis in FP32, against the FP64 oracle
+    prec, tol = PRECS[name]
+    dims, order, x, ref = rows512
+    extra = fftrw.FLAG_FUSED_FFT if mode == "fused" else fftrw.FLAG_SEPARATE
+    plan = fftrw.Plan(dims, 4096, order, precision=prec, flags=fftrw.FLAG_COUNT_MOVED | extra)
+    desc = plan.describe()[1]
+    assert desc.startswith("fused|") == (mode == "fused")
+    assert (desc.count("mfma:16x16x2") == 2) == (prec != fftrw.PREC_NATIVE), desc
+    xd = to_dev(x)
+    yd = empty_dev(dims, np.complex64)
+    plan.exec_fwd(xd, yd)
+    y = to_host(yd)
+    err = dft.rel_l2(y, ref)
+    print(f"{dims} {name} {mode}: rel-L2 {err:.3e} max-abs/max|ref| {dft.max_abs_rel(y, ref):.3e}", flush=True)
+    assert err < tol
+    zd = empty_dev(dims, np.complex64)
+    plan.exec_inv(yd, zd)
+    assert dft.rel_l2(to_host(zd), x) < 2 * tol
+    analytic, moved = plan.stats()
+    assert moved == analytic
