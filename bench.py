@@ -65,6 +65,11 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def progress(what):
+    """One line on stderr as each leg of the run ends (the JSON line goes to stdout)."""
+    print(f"bench: {what}", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(dims, x_host):
     """The FP64 oracle, as it stands, on a bounded sample: every axis's 1-D FFT
     pass over a quarter of the array (whole rows), scaled to one transform; then
@@ -475,6 +480,7 @@ def main():
     out["unfused_pipeline"] = {"ms_per_transform": round(ms_plain, 4),
                                "GFLOPs": round(flops_per_transform / (ms_plain * 1e-3) / 1e9, 1),
                                "stage_ms": [round(v, 4) for v in st_plain]}
+    progress("headline and separate pipeline done")
     if args.staged:
         # explicit per-process buffers: pack, exchange of exactly the moved
         # points, unpack (the exchange's traffic is 2 x 8 x V_t bytes)
@@ -497,10 +503,13 @@ def main():
     if not args.no_forms:
         torch.cuda.empty_cache()
         out["precision_form"] = precision_forms(args.steps)
+        progress("precision forms at 256^3 done")
         torch.cuda.empty_cache()
         out["precision_form_512cube"] = precision_forms(args.steps, (512, 512, 512), 4096)
+        progress("precision forms at 512^3 done")
         torch.cuda.empty_cache()
         out["batched_form"] = batched_form(max(5, args.steps // 2))
+        progress("batched form done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dims, x_host)
     print(json.dumps(out), flush=True)
