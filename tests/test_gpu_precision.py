@@ -87,7 +87,7 @@ def test_256cube_precision_forms(gpu_lib, cube256, name, kind, mode):
 def test_fused_mfma_matches_separate_steps(gpu_lib, name, dims, P, oidx):
     # the MFMA transform fused with the transpose that follows runs the same
     # per-row arithmetic as the separate MFMA step; N_v = 40, 24, 12 and 27
-    # leave ragged groups of 16 (256-point rows) or 8 rows (512-point rows)
+    # leave ragged groups of 16 rows
     prec, _ = PRECS[name]
     order = fftrw.fft_order_at(len(dims), oidx)
     x = inputs.uniform(dims, 44, np.complex64)
