@@ -12,6 +12,7 @@
 #include <cstring>
 #include <limits>
 #include <numeric>
+#include <queue>
 
 namespace fftrw {
 
@@ -291,55 +292,113 @@ std::vector<PairCount> pair_counts(const Layout &a, const Layout &b)
 
 namespace {
 
-// Dense Hungarian algorithm (minimum cost, potentials), n x n, 1-based
-// internally.  Returns col_of_row (0-based).
-std::vector<int> hungarian_min(int n, const std::vector<i64> &cost)
+// Maximum-weight bipartite matching on a sparse graph, exactly: rows
+// 0..nr-1, columns 0..nc-1, adj[i] = (column, weight > 0).  Written as a
+// rectangular assignment of every row, either to a real column at cost
+// W - w or to a private "unmatched" column at cost W (W = the largest
+// weight), so all costs are non-negative and the minimum cost is
+// nr W - (the maximum matched weight).  Rows are assigned one at a time by a
+// shortest augmenting path: Dijkstra over reduced costs c + phi(row) -
+// phi(col) (never negative), through matched edges back to their rows, until
+// a free column is reached; the potentials of the scanned nodes then move by
+// their distance less the path's, which keeps every reduced cost
+// non-negative and the matched edges tight.  A row reduction first makes
+// each row's cheapest edge tight and matches the rows whose cheapest column
+// is free, so only the contested rows search.  Integer costs throughout, and
+// the search stays near the row, so a banded overlap graph of any size
+// costs about its number of edges per row.  Returns col_of_row (-1 if the
+// row stays unmatched).
+std::vector<i64> sparse_max_matching(i64 nr, i64 nc, const std::vector<std::vector<std::pair<i64, i64>>> &adj)
 {
+    i64 W = 1;
+    for (const auto &a : adj)
+        for (const auto &e : a) W = std::max(W, e.second);
     const i64 INF = std::numeric_limits<i64>::max() / 4;
-    std::vector<i64> u(n + 1, 0), v(n + 1, 0), minv(n + 1);
-    std::vector<int> pr(n + 1, 0), way(n + 1, 0);
-    std::vector<char> used(n + 1);
-    for (int i = 1; i <= n; ++i) {
-        pr[0] = i;
-        int j0 = 0;
-        std::fill(minv.begin(), minv.end(), INF);
-        std::fill(used.begin(), used.end(), 0);
-        do {
-            used[j0] = 1;
-            int i0 = pr[j0], j1 = 0;
-            i64 delta = INF;
-            for (int j = 1; j <= n; ++j) {
-                if (used[j]) continue;
-                i64 cur = cost[(size_t)(i0 - 1) * n + (j - 1)] - u[i0] - v[j];
-                if (cur < minv[j]) {
-                    minv[j] = cur;
-                    way[j] = j0;
-                }
-                if (minv[j] < delta) {
-                    delta = minv[j];
-                    j1 = j;
-                }
+    const i64 ncol = nc + nr;  // real columns, then row i's private column nc + i
+    std::vector<i64> phi_r(nr, 0), phi_c(ncol, 0);
+    std::vector<i64> row_of(ncol, -1), col_of(nr, -1);
+    std::vector<i64> dist(ncol, INF), pred(ncol, -1);
+    std::vector<char> done(ncol, 0);
+    std::vector<i64> touched;
+    using QE = std::pair<i64, i64>;
+    std::priority_queue<QE, std::vector<QE>, std::greater<QE>> pq;
+    auto relax = [&](i64 i, i64 di) {
+        // edges of row i leaving to columns other than its own matched one
+        auto edge = [&](i64 k, i64 c) {
+            if (done[k] || k == col_of[i]) return;
+            const i64 nd = di + c + phi_r[i] - phi_c[k];
+            if (nd < dist[k]) {
+                if (dist[k] == INF) touched.push_back(k);
+                dist[k] = nd;
+                pred[k] = i;
+                pq.push({nd, k});
             }
-            for (int j = 0; j <= n; ++j) {
-                if (used[j]) {
-                    u[pr[j]] += delta;
-                    v[j] -= delta;
-                } else {
-                    minv[j] -= delta;
-                }
+        };
+        for (const auto &e : adj[(size_t)i]) edge(e.first, W - e.second);
+        edge(nc + i, W);
+    };
+    // row reduction: phi(row) = -(its cheapest cost) makes that edge tight;
+    // rows whose cheapest column is still free take it at once
+    for (i64 i = 0; i < nr; ++i) {
+        i64 best = W, bk = nc + i;
+        for (const auto &e : adj[(size_t)i])
+            if (W - e.second < best || (W - e.second == best && e.first < bk)) {
+                best = W - e.second;
+                bk = e.first;
             }
-            j0 = j1;
-        } while (pr[j0] != 0);
-        do {
-            int j1 = way[j0];
-            pr[j0] = pr[j1];
-            j0 = j1;
-        } while (j0);
+        phi_r[i] = -best;
+        if (row_of[bk] < 0) {
+            row_of[bk] = i;
+            col_of[i] = bk;
+        }
     }
-    std::vector<int> col_of_row(n, -1);
-    for (int j = 1; j <= n; ++j)
-        if (pr[j] > 0) col_of_row[pr[j] - 1] = j - 1;
-    return col_of_row;
+    std::vector<i64> rows_seen;
+    for (i64 s = 0; s < nr; ++s) {
+        if (col_of[s] >= 0) continue;
+        touched.clear();
+        rows_seen.assign(1, s);
+        std::vector<i64> drow(1, 0);
+        relax(s, 0);
+        i64 sink = -1, D = 0;
+        std::vector<i64> scanned;
+        while (!pq.empty()) {
+            const auto [d, k] = pq.top();
+            pq.pop();
+            if (done[k] || d != dist[k]) continue;
+            done[k] = 1;
+            scanned.push_back(k);
+            if (row_of[k] < 0) {
+                sink = k;
+                D = d;
+                break;
+            }
+            const i64 i = row_of[k];  // the matched edge back is tight: distance d
+            rows_seen.push_back(i);
+            drow.push_back(d);
+            relax(i, d);
+        }
+        while (!pq.empty()) pq.pop();
+        // potentials: scanned nodes move by (distance - D), the rest by 0
+        // (a common shift of every node leaves reduced costs unchanged)
+        for (i64 k : scanned) phi_c[k] += dist[k] - D;
+        for (size_t t = 0; t < rows_seen.size(); ++t) phi_r[rows_seen[t]] += drow[t] - D;
+        // augment along the predecessors from the sink back to s
+        for (i64 k = sink; k >= 0;) {
+            const i64 i = pred[k];
+            const i64 prev = col_of[i];
+            col_of[i] = k;
+            row_of[k] = i;
+            k = (i == s) ? -1 : prev;
+        }
+        for (i64 k : touched) {
+            dist[k] = INF;
+            done[k] = 0;
+            pred[k] = -1;
+        }
+    }
+    std::vector<i64> out(nr, -1);
+    for (i64 i = 0; i < nr; ++i) out[i] = col_of[i] < nc ? col_of[i] : -1;
+    return out;
 }
 
 struct DSU {
@@ -370,30 +429,26 @@ Status max_matching(i64 P, const std::vector<PairCount> &pc, i64 *weight, std::v
 
     std::vector<i64> m(P, -1);
     std::vector<char> col_taken(P, 0);
+    std::vector<i64> ridx(P, -1), cidx(P, -1);
     i64 total = 0;
     for (i64 c = 0; c < 2 * P; ++c) {
         if (edges_of[c].empty()) continue;
         const auto &R = rows_of[c];
         const auto &C = cols_of[c];
-        i64 n = std::max<i64>((i64)R.size(), (i64)C.size());
-        if (n > kMaxMatchP)
-            return Status::err(-7, "matched ownership: overlap component too large for the exact solver");
-        std::vector<i64> ridx(P, -1), cidx(P, -1);
         for (size_t i = 0; i < R.size(); ++i) ridx[R[i]] = (i64)i;
         for (size_t j = 0; j < C.size(); ++j) cidx[C[j]] = (i64)j;
-        std::vector<i64> cost((size_t)(n * n), 0);
-        for (const PairCount &e : edges_of[c]) cost[(size_t)(ridx[e.p] * n + cidx[e.q])] = -e.n;
-        std::vector<int> col = hungarian_min((int)n, cost);
+        std::vector<std::vector<std::pair<i64, i64>>> adj(R.size());
+        for (const PairCount &e : edges_of[c]) adj[(size_t)ridx[e.p]].push_back({cidx[e.q], e.n});
+        const std::vector<i64> col = sparse_max_matching((i64)R.size(), (i64)C.size(), adj);
         for (size_t i = 0; i < R.size(); ++i) {
-            int j = col[i];
-            if (j >= 0 && j < (int)C.size()) {
-                i64 w = -cost[(size_t)(i * n + j)];
-                if (w > 0) {
-                    m[R[i]] = C[j];
-                    col_taken[C[j]] = 1;
-                    total += w;
+            const i64 j = col[i];
+            if (j < 0) continue;
+            for (const auto &e : adj[i])
+                if (e.first == j) {
+                    m[R[i]] = C[(size_t)j];
+                    col_taken[(size_t)C[(size_t)j]] = 1;
+                    total += e.second;
                 }
-            }
         }
     }
     // complete the permutation with the remaining (zero-overlap) pairs

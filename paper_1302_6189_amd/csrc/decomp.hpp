@@ -82,9 +82,8 @@ struct PairCount {
 std::vector<PairCount> pair_counts(const Layout &a, const Layout &b);
 
 // Maximum-weight perfect matching on a P x P overlap given sparsely; returns
-// the matched weight and mu[p] = q.  Exact (Hungarian algorithm with
-// potentials on the dense matrix); P <= kMaxMatchP.
-constexpr i64 kMaxMatchP = 2048;
+// the matched weight and mu[p] = q.  Exact (shortest augmenting paths over
+// the sparse overlap graph, one connected component at a time).
 Status max_matching(i64 P, const std::vector<PairCount> &pc, i64 *weight, std::vector<i64> *mu);
 
 // Transpose a -> b amount under ownership 0 (literal) / 1 (matched);

@@ -80,7 +80,7 @@ def test_random_plans_matched(gpu_lib, dims, P, idx, mode, dtype):
             assert mode == "staged"
             assert any(decomp.level([dims[a] for a in p], P) >= M for p in order)
         else:
-            assert e.code == fftrw.E_UNSUPPORTED  # an overlap component past the exact assignment's limit
+            raise
         return
     x = inputs.uniform(dims, 3, np.complex64)
     xd = to_dev(x)

@@ -82,6 +82,19 @@ def test_comm_volume_matched_matches_oracle(dims, P):
         assert (steps, ret) == (want_steps, want_ret)
 
 
+@pytest.mark.parametrize("dims,P,orders_", [((64, 64, 64), 3000, (0, 5)), ((40, 36, 30), 2500, (1, 6)),
+                                             ((24, 20, 18, 10), 2600, (0, 200))])
+def test_comm_volume_matched_large_components(dims, P, orders_):
+    # ragged N_p chains the overlap graph into components of more than 2,048
+    # ranges: the sparse exact matching against the oracle's dense assignment
+    M = len(dims)
+    for idx in orders_:
+        o = fftrw.fft_order_at(M, idx)
+        want_steps, want_ret = decomp.order_volumes(dims, P, o, ownership="matched")
+        steps, tot, ret = fftrw.fft_comm_volume(dims, P, o, ownership=fftrw.OWN_MATCHED, allow_rowsplit=True)
+        assert (steps, ret) == (want_steps, want_ret), fftrw.order_to_str(o)
+
+
 @pytest.mark.parametrize("dims,P", [((5, 6, 7), 11), ((8, 8, 8), 64), ((4, 6, 5, 3), 50), ((3, 4, 5, 2, 3), 33)])
 def test_pair_counts_match_oracle(dims, P):
     M = len(dims)
