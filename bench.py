@@ -70,10 +70,12 @@ def progress(what):
     print(f"bench: {what}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(dims, x_host):
+def cpu_baseline(dims, x_host, P, order):
     """The FP64 oracle, as it stands, on a bounded sample: every axis's 1-D FFT
     pass over a quarter of the array (whole rows), scaled to one transform; then
-    the same on one thread over a sixteenth of the array."""
+    the same on one thread over a sixteenth of the array; and the oracle's
+    point-by-point owner counting of one order's amounts (the order search
+    repeats it for every order) beside the library's whole search."""
     import numpy as np
 
     from oracle import dft
@@ -102,7 +104,31 @@ def cpu_baseline(dims, x_host):
             "one_thread": {"value": round(5 * T * math.log2(T) / full1 / 1e9, 3), "unit": "GFLOP/s",
                            "sample": f"each axis's pass over 1/16 of the array on one thread ({sec1:.2f} s, "
                                      f"x{dims[0] // S1})"},
+            "order_amounts": order_amounts(dims, P, order),
             "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def order_amounts(dims, P, order):
+    """Seconds for the oracle's amounts of one transpose order (its transposes
+    and the return, from per-process owner counts) and for the library's exact
+    search over all orders."""
+    from oracle import decomp
+    from paper_1302_6189_amd import fftrw
+    M = len(dims)
+    t0 = time.perf_counter()
+    steps, ret = decomp.order_volumes(dims, P, order)
+    sec = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    search = fftrw.fft_order_search(dims, P)
+    lib_sec = time.perf_counter() - t0
+    lib_steps, _, lib_ret = fftrw.fft_comm_volume(dims, P, order)
+    n = fftrw.fft_order_count(M)
+    return {"oracle_s_per_order": round(sec, 2), "orders": n,
+            "oracle_s_all_orders": round(sec * n, 1), "library_search_s": round(lib_sec, 4),
+            "amounts_equal": [int(v) for v in steps] == list(lib_steps) and int(ret) == lib_ret,
+            "best_order": fftrw.order_to_str(search["best_order"]),
+            "sample": f"the oracle's literal amounts of order {fftrw.order_to_str(order)} at N_p = {P} "
+                      f"(x{n} for every order)"}
 
 
 def time_fwd(plan, x, y, stream, reps, warm=3):
@@ -511,7 +537,7 @@ def main():
         out["batched_form"] = batched_form(max(5, args.steps // 2))
         progress("batched form done")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(dims, x_host)
+        out["cpu_baseline"] = cpu_baseline(dims, x_host, P, order)
     print(json.dumps(out), flush=True)
 
 
